@@ -1,0 +1,136 @@
+/*
+ * CPU oracle for the energy-efficient dynamic flexible flow shop (EDFFS) and
+ * its priority-based hybrid parallel GA (Luo, Fujimura, El Baz,
+ * arXiv 1903.10741).
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the plain, slow, obviously
+ * correct statement of what the GPU path computes. Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it. The GPU
+ * library never includes this header nor links this code, and this code never
+ * includes anything from the GPU library.
+ *
+ * Conventions (all integer):
+ *   times int32, objective int64, power int32;
+ *   arrays row-major, caller-owned; no function keeps a pointer past return.
+ *   Return 0 on success or a negative ORC_E_* code.
+ */
+#ifndef FFS_ORACLE_H
+#define FFS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_OK 0
+#define ORC_E_INVAL (-1)       /* bad shape, not a permutation, order breaks route */
+#define ORC_E_INFEASIBLE (-2)  /* some Q_jsm > Q_max: no start time can ever fit */
+#define ORC_E_NOMEM (-3)
+
+/* One event's instance: all jobs known so far (original and arrived, J u J'),
+ * plus the state frozen at the rescheduling point RS (Section 4.1). */
+typedef struct {
+  int32_t n_jobs, n_stages, o_max;
+  const int32_t *n_machines;   /* [g] machines per stage, 1 <= o_s <= o_max */
+  const int32_t *proc;         /* [n_jobs][g][o_max] P_jsm >= 1 */
+  const int32_t *power;        /* [n_jobs][g][o_max] Q_jsm >= 1 */
+  const int32_t *release;      /* [n_jobs] R_j */
+  const int32_t *due;          /* [n_jobs] D_j */
+  int32_t q_max, wt, rs;       /* Q_max, WT, rescheduling point RS */
+  const int32_t *first_stage;  /* [n_jobs] first stage not frozen; g = all frozen */
+  const int32_t *ready;        /* [n_jobs] earliest start of stage first_stage */
+  const int32_t *machine_free; /* [g][o_max] end of the last frozen op per machine */
+  int32_t n_running;
+  const int32_t *running;      /* [n_running][2] (end, q): power held on [RS, end) */
+  int64_t frozen_tardiness;    /* sum of T_j over jobs with every op frozen */
+  int32_t frozen_cmax;         /* max C_j over those jobs (0 if none) */
+  int32_t n_active;
+  const int32_t *active;       /* [n_active] job ids with first_stage < g; gene k <-> active[k] */
+} orc_instance;
+
+/* Counter-based generator Philox4x64 with 10 rounds (Salmon, Moraes, Dror,
+ * Shaw, SC'11), written from its published description. */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Upper bound (slots after RS) on any completion time a decode can produce. */
+int64_t orc_horizon_bound(const orc_instance *in);
+
+/* Decode one job-priority vector prio[n_active] (a permutation of 1..n_active,
+ * larger = higher priority) into a schedule and its objective, eq. (1).
+ * start/mach ([n_jobs][g], may be NULL): entries of decoded ops are written,
+ * entries of frozen ops are left untouched. work (may be NULL): algorithmic
+ * operation count of this decode: per op 3*o_s for the machine choice, plus
+ * (S - t0) + p slots examined by the push-right from its first candidate
+ * start t0, plus p slots updated. */
+int orc_decode(const orc_instance *in, const int32_t *prio, int64_t *obj,
+               int32_t *start, int32_t *mach, int64_t *work);
+
+/* Decode pop vectors prio[pop][n_active]; OpenMP over chromosomes. */
+int orc_decode_pop(const orc_instance *in, const int32_t *prio, int32_t pop,
+                   int64_t *obj, int64_t *work, int32_t n_threads);
+
+/* Operation-level decode (the paper's own X/Z form): place ops[n_ops][3] =
+ * (job, stage, machine) in the given order; machine -1 picks the earliest
+ * completion machine. Every op must be its job's next unplaced stage. If
+ * every unfrozen op is placed, *obj gets eq. (1); otherwise *obj = -1. */
+int orc_decode_ops(const orc_instance *in, int32_t n_ops, const int32_t *ops,
+                   int64_t *obj, int32_t *start, int32_t *mach);
+
+/* GA parameters. An island is a rows x cols torus; islands are contiguous. */
+typedef struct {
+  int32_t islands, rows, cols;
+  uint32_t pc, pm;             /* crossover / mutation if hi32(draw) < threshold */
+  int32_t mig_interval, mig_k; /* ring migration every mig_interval generations */
+} orc_ga_params;
+
+/* Population init (generation 0): Fisher-Yates from Philox purpose 0, decode,
+ * elite = island best. Outputs prio[pop][n_active], obj[pop],
+ * elite[islands][n_active], elite_obj[islands]. */
+int orc_ga_init(const orc_instance *in, const orc_ga_params *gp, uint64_t seed,
+                uint64_t shop, int32_t event, int32_t *prio, int64_t *obj,
+                int32_t *elite, int64_t *elite_obj, int32_t n_threads);
+
+/* One generation gen >= 1: selection, crossover + correction, mutation,
+ * decode, replacement, then migration when gen % mig_interval == 0.
+ * Reads *_in, writes *_out (distinct buffers). island_sel (may be NULL = all):
+ * only islands with island_sel[i] != 0 are written to the outputs; the
+ * entries of other islands in the outputs are unspecified. */
+int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
+                      uint64_t seed, uint64_t shop, int32_t event, int32_t gen,
+                      const int32_t *prio_in, const int64_t *obj_in,
+                      const int32_t *elite_in, const int64_t *elite_obj_in,
+                      int32_t *prio_out, int64_t *obj_out,
+                      int32_t *elite_out, int64_t *elite_obj_out,
+                      const uint8_t *island_sel, int32_t n_threads);
+
+/* GA building blocks, exposed for the tests. */
+void orc_crossover(int32_t n, const int32_t *a, const int32_t *b, int32_t cut,
+                   int32_t *child_a, int32_t *child_b);
+void orc_correct(int32_t n, int32_t *v);
+void orc_mutate(int32_t n, int32_t *v, uint64_t w1, uint64_t w2);  /* n >= 2 */
+
+/* Predictive-reactive rescheduling (Section 4.1, eq. (10)): freeze every op of
+ * the executed plan that started before rs, append the n_new arrived jobs and
+ * produce the next event's instance. */
+typedef struct {
+  int32_t *proc, *power;       /* [n_jobs + n_new][g][o_max] */
+  int32_t *release, *due, *first_stage, *ready;  /* [n_jobs + n_new] */
+  int32_t *machine_free;       /* [g][o_max] */
+  int32_t *running;            /* [g * o_max][2]: a machine runs at most one op at RS */
+  int32_t *active;             /* [n_jobs + n_new] */
+  int32_t n_jobs, n_running, n_active;
+  int64_t frozen_tardiness;
+  int32_t frozen_cmax;
+} orc_resched_out;
+
+int orc_reschedule(const orc_instance *prev, const int32_t *plan_start,
+                   const int32_t *plan_mach, int32_t rs, int32_t n_new,
+                   const int32_t *new_proc, const int32_t *new_power,
+                   const int32_t *new_release, const int32_t *new_due,
+                   orc_resched_out *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,284 @@
+"""Seeded synthetic EDFFS workloads.
+
+This module only draws inputs: instances, arrival events, GA parameters and
+random priority populations. It holds none of the method's arithmetic (no
+decoding, no GA operator, no rescheduling) and serves the GPU path, the
+tests and the benchmark alike.
+
+The paper's experiments use random instances drawn from its Table 5
+distributions, with no seeds published and no public benchmark; the recipes
+below are synthetic stand-ins with the shapes of the configurations this
+project measures (job counts, stages, machines per stage, processing-time
+and power distributions, peak-power fraction, arrival events).
+
+Draws use numpy's PCG64 generator (``numpy.random.default_rng(seed)``) in the
+order written in each recipe. Rounding is half-up: ``floor(x + 0.5)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+PC_09 = 3865470566   # floor(0.9 * 2^32): crossover threshold on hi32 of a draw
+PM_01 = 429496729    # floor(0.1 * 2^32): mutation threshold
+
+
+@dataclass
+class Instance:
+    """One event's EDFFS instance (field meanings follow the C header)."""
+    n_jobs: int
+    n_stages: int
+    o_max: int
+    n_machines: np.ndarray   # int32 [g]
+    proc: np.ndarray         # int32 [n_jobs, g, o_max]
+    power: np.ndarray        # int32 [n_jobs, g, o_max]
+    release: np.ndarray      # int32 [n_jobs]
+    due: np.ndarray          # int32 [n_jobs]
+    q_max: int
+    wt: int
+    rs: int
+    first_stage: np.ndarray  # int32 [n_jobs]
+    ready: np.ndarray        # int32 [n_jobs]
+    machine_free: np.ndarray  # int32 [g, o_max]
+    running: np.ndarray      # int32 [n_running, 2] (end, q)
+    frozen_tardiness: int
+    frozen_cmax: int
+    active: np.ndarray       # int32 [n_active]
+
+    @property
+    def n_active(self) -> int:
+        return int(len(self.active))
+
+    @classmethod
+    def from_fields(cls, d: dict) -> "Instance":
+        return cls(**{k: d[k] for k in cls.__dataclass_fields__})
+
+
+@dataclass
+class Arrival:
+    """New jobs arriving at rescheduling point rs."""
+    rs: int
+    proc: np.ndarray     # int32 [n_new, g, o_max]
+    power: np.ndarray    # int32 [n_new, g, o_max]
+    release: np.ndarray  # int32 [n_new]
+    due: np.ndarray      # int32 [n_new]
+
+
+@dataclass
+class GaParams:
+    islands: int
+    rows: int
+    cols: int
+    pc: int = PC_09
+    pm: int = PM_01
+    mig_interval: int = 10
+    mig_k: int = 1
+
+    @property
+    def pop(self) -> int:
+        return self.islands * self.rows * self.cols
+
+
+@dataclass
+class Workload:
+    name: str
+    initial: Instance
+    arrivals: List[Arrival]
+    ga: GaParams
+    generations: int
+    seed: int
+    shop: int = 0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def decodes_per_run(self) -> int:
+        """Decodes in one full run: (generation 0 + generations) per slot per event."""
+        return (1 + len(self.arrivals)) * (1 + self.generations) * self.ga.pop
+
+
+def round_half_up(x):
+    return np.floor(np.asarray(x, dtype=np.float64) + 0.5).astype(np.int64)
+
+
+def initial_instance(proc, power, release, due, n_machines, q_max, wt) -> Instance:
+    """The state at time 0: nothing scheduled, every job active from stage 0."""
+    proc = np.ascontiguousarray(proc, dtype=np.int32)
+    n, g, om = proc.shape
+    return Instance(
+        n_jobs=n, n_stages=g, o_max=om,
+        n_machines=np.ascontiguousarray(n_machines, dtype=np.int32),
+        proc=proc, power=np.ascontiguousarray(power, dtype=np.int32),
+        release=np.ascontiguousarray(release, dtype=np.int32),
+        due=np.ascontiguousarray(due, dtype=np.int32),
+        q_max=int(q_max), wt=int(wt), rs=0,
+        first_stage=np.zeros(n, np.int32),
+        ready=np.ascontiguousarray(release, dtype=np.int32).copy(),
+        machine_free=np.zeros((g, om), np.int32),
+        running=np.zeros((0, 2), np.int32),
+        frozen_tardiness=0, frozen_cmax=0,
+        active=np.arange(n, dtype=np.int32),
+    )
+
+
+def peak_limit(machine_power, n_machines, percent):
+    """Q_max = max(floor(percent * sum_s max_m Q_sm / 100), max Q_sm).
+
+    The second term keeps every single op placeable (no op may need more than
+    the peak on its own)."""
+    g = len(n_machines)
+    stage_max = [int(machine_power[s, :n_machines[s]].max()) for s in range(g)]
+    return max((percent * sum(stage_max)) // 100, max(stage_max))
+
+
+def mean_proc(proc, n_machines):
+    """P-bar_j = sum_s mean_m P_jsm (the paper's Table 5 definition)."""
+    g = len(n_machines)
+    return np.array([sum(proc[j, s, :n_machines[s]].mean() for s in range(g))
+                     for j in range(proc.shape[0])], dtype=np.float64)
+
+
+def _broadcast_power(machine_power, n_jobs):
+    return np.ascontiguousarray(np.broadcast_to(machine_power[None], (n_jobs,) + machine_power.shape),
+                                dtype=np.int32)
+
+
+def _poisson_times(rng, n_events, lb0):
+    """Arrival times: floored exponential gaps of mean lb0/(n_events+1), each >= 1."""
+    t = 0
+    out = []
+    mean = lb0 / (n_events + 1)
+    for _ in range(n_events):
+        t += max(1, int(math.floor(rng.exponential(mean))))
+        out.append(t)
+    return out
+
+
+def makespan_lower_bound(proc, machine_power, n_machines, q_max):
+    """LB0 = max(max_s ceil(sum_j min_m P_jsm / o_s), ceil(sum_js min_m P_jsm Q_sm / Q_max))."""
+    n, g, _ = proc.shape
+    per_stage = []
+    energy = 0
+    for s in range(g):
+        o = int(n_machines[s])
+        per_stage.append(math.ceil(int(proc[:, s, :o].min(axis=1).sum()) / o))
+        energy += int((proc[:, s, :o] * machine_power[s, :o][None]).min(axis=1).sum())
+    return max(max(per_stage), math.ceil(energy / q_max))
+
+
+def config1(seed: int = 0) -> Workload:
+    """Tiny: 10 jobs, 2 stages, 2 identical machines; P ~ U{1..20}; Q_sm ~ U{1..10};
+    peak 60%; R = 0, D = round(U[1.2,2.0] * P-bar); one event at t=15 adding 3 jobs;
+    WT = 10; 64 individuals in one 8x8 island; 50 generations per event."""
+    rng = np.random.default_rng(seed)
+    n0, g, o = 10, 2, 2
+    p_js = rng.integers(1, 21, size=(n0, g))
+    proc = np.repeat(p_js[:, :, None], o, axis=2)
+    qsm = rng.integers(1, 11, size=(g, o))
+    nm = np.full(g, o, np.int32)
+    q_max = peak_limit(qsm, nm, 60)
+    slack = rng.uniform(1.2, 2.0, size=n0)
+    due = round_half_up(slack * mean_proc(proc, nm))
+    inst = initial_instance(proc, _broadcast_power(qsm, n0), np.zeros(n0), due, nm, q_max, 10)
+    n_new, t = 3, 15
+    p_new = np.repeat(rng.integers(1, 21, size=(n_new, g))[:, :, None], o, axis=2)
+    slack = rng.uniform(1.2, 2.0, size=n_new)
+    arr = Arrival(rs=t, proc=p_new.astype(np.int32), power=_broadcast_power(qsm, n_new),
+                  release=np.full(n_new, t, np.int32),
+                  due=(t + round_half_up(slack * mean_proc(p_new, nm))).astype(np.int32))
+    return Workload("tiny-10x2x2", inst, [arr], GaParams(1, 8, 8, mig_k=1), 50, seed)
+
+
+def _unrelated(rng, n, speed):
+    base = rng.integers(5, 51, size=(n, speed.shape[0]))
+    return np.maximum(1, round_half_up(base[:, :, None] * speed[None])).astype(np.int32)
+
+
+def config2(seed: int = 0, generations: int = 500) -> Workload:
+    """Paper-shaped: 50 jobs, 5 stages, 3 unrelated machines, P = max(1, round(base*speed)),
+    base ~ U{5..50}, speed_sm ~ U[0.8,1.5]; Q_sm ~ U{2..15}; peak 55%; R = 0;
+    5 Poisson arrival events of U{5..10} jobs (due slack U[1.2,2.0]);
+    population 4096 = 32 islands x (8x16), 2 best migrate every 10 generations."""
+    rng = np.random.default_rng(seed)
+    n0, g, o, n_events = 50, 5, 3, 5
+    speed = rng.uniform(0.8, 1.5, size=(g, o))
+    proc = _unrelated(rng, n0, speed)
+    qsm = rng.integers(2, 16, size=(g, o))
+    nm = np.full(g, o, np.int32)
+    q_max = peak_limit(qsm, nm, 55)
+    slack = rng.uniform(1.2, 2.0, size=n0)
+    due = round_half_up(slack * mean_proc(proc, nm))
+    inst = initial_instance(proc, _broadcast_power(qsm, n0), np.zeros(n0), due, nm, q_max, 10)
+    times = _poisson_times(rng, n_events, makespan_lower_bound(proc, qsm, nm, q_max))
+    arrivals = []
+    for t in times:
+        k = int(rng.integers(5, 11))
+        p_new = _unrelated(rng, k, speed)
+        sl = rng.uniform(1.2, 2.0, size=k)
+        arrivals.append(Arrival(t, p_new, _broadcast_power(qsm, k), np.full(k, t, np.int32),
+                                (t + round_half_up(sl * mean_proc(p_new, nm))).astype(np.int32)))
+    return Workload("paper-50x5x3", inst, arrivals, GaParams(32, 8, 16, mig_k=2), generations, seed)
+
+
+def config3(seed: int = 0, generations: int = 200) -> Workload:
+    """Large: 200 jobs, 10 stages, o_s ~ U{4..6} unrelated machines, P ~ U{1..100} i.i.d.,
+    Q_sm ~ U{1..20}, peak 50%; 10 events of U{10..30} jobs; 512 islands x (8x16)."""
+    rng = np.random.default_rng(seed)
+    n0, g, om, n_events = 200, 10, 6, 10
+    nm = rng.integers(4, 7, size=g).astype(np.int32)
+    proc = rng.integers(1, 101, size=(n0, g, om)).astype(np.int32)
+    qsm = rng.integers(1, 21, size=(g, om))
+    q_max = peak_limit(qsm, nm, 50)
+    slack = rng.uniform(1.2, 2.0, size=n0)
+    due = round_half_up(slack * mean_proc(proc, nm))
+    inst = initial_instance(proc, _broadcast_power(qsm, n0), np.zeros(n0), due, nm, q_max, 10)
+    times = _poisson_times(rng, n_events, makespan_lower_bound(proc, qsm, nm, q_max))
+    arrivals = []
+    for t in times:
+        k = int(rng.integers(10, 31))
+        p_new = rng.integers(1, 101, size=(k, g, om)).astype(np.int32)
+        sl = rng.uniform(1.2, 2.0, size=k)
+        arrivals.append(Arrival(t, p_new, _broadcast_power(qsm, k), np.full(k, t, np.int32),
+                                (t + round_half_up(sl * mean_proc(p_new, nm))).astype(np.int32)))
+    return Workload("large-200x10x4-6", inst, arrivals, GaParams(512, 8, 16, mig_k=2), generations,
+                    seed)
+
+
+def random_instance(seed: int, n_jobs: int, n_stages: int, machines, p_max: int = 20,
+                    q_range=(1, 10), percent: int = 60, release_max: int = 0,
+                    wt: int = 10) -> Instance:
+    """A small random event-0 instance for tests. `machines` is an int (all stages)
+    or a list of per-stage machine counts."""
+    rng = np.random.default_rng(seed)
+    nm = np.array([machines] * n_stages if np.isscalar(machines) else machines, np.int32)
+    om = int(nm.max())
+    proc = rng.integers(1, p_max + 1, size=(n_jobs, n_stages, om)).astype(np.int32)
+    qsm = rng.integers(q_range[0], q_range[1] + 1, size=(n_stages, om))
+    q_max = peak_limit(qsm, nm, percent)
+    release = rng.integers(0, release_max + 1, size=n_jobs) if release_max else np.zeros(n_jobs)
+    slack = rng.uniform(1.2, 2.0, size=n_jobs)
+    due = release + round_half_up(slack * mean_proc(proc, nm))
+    return initial_instance(proc, _broadcast_power(qsm, n_jobs), release, due, nm, q_max, wt)
+
+
+def random_arrival(seed: int, inst: Instance, rs: int, n_new: int, p_max: int = 20) -> Arrival:
+    rng = np.random.default_rng(seed)
+    g, om = inst.n_stages, inst.o_max
+    proc = rng.integers(1, p_max + 1, size=(n_new, g, om)).astype(np.int32)
+    power = np.ascontiguousarray(np.broadcast_to(inst.power[0][None], (n_new, g, om))
+                                 if inst.n_jobs else np.ones((n_new, g, om)), dtype=np.int32)
+    slack = rng.uniform(1.2, 2.0, size=n_new)
+    due = rs + round_half_up(slack * mean_proc(proc, inst.n_machines))
+    return Arrival(rs, proc, power, np.full(n_new, rs, np.int32), due.astype(np.int32))
+
+
+def random_population(seed: int, pop: int, n: int) -> np.ndarray:
+    """pop random permutations of 1..n, int32 [pop, n]."""
+    rng = np.random.default_rng(seed)
+    base = np.tile(np.arange(1, n + 1, dtype=np.int32), (pop, 1))
+    return np.ascontiguousarray(rng.permuted(base, axis=1), dtype=np.int32)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3}
