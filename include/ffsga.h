@@ -1,0 +1,206 @@
+/*
+ * ffsga: MI355X (gfx950) library for the hot path of the priority-based hybrid
+ * parallel GA for the energy-efficient dynamic flexible flow shop (EDFFS) of
+ * Luo, Fujimura and El Baz (arXiv 1903.10741).
+ *
+ * The problem (Section 3): jobs J u J' go through g stages in order; stage s
+ * has o_s parallel machines; op (j,s) on machine m takes P_jsm time and draws
+ * Q_jsm power; the total power at every instant stays within Q_max (eqs.
+ * (7)-(9)); the objective is WT * total tardiness + makespan (eq. (1)).
+ * New jobs arriving at a rescheduling point RS trigger predictive-reactive
+ * complete rescheduling (Section 4.1): ops started before RS are frozen, every
+ * other op is rescheduled no earlier than RS (eq. (10)).
+ *
+ * The chromosome is one priority per unfrozen job (larger = higher, Section
+ * 4.3); a decode places ops stage by stage in decreasing priority, each on
+ * the machine of earliest completion, after that machine's earlier ops, at
+ * the earliest start whose power window fits under Q_max (Algorithm 2).
+ *
+ * Conventions
+ *   - Every pointer marked "device" is GPU memory owned by the caller; the
+ *     library keeps no pointer past a call except inside a caller-owned
+ *     ffs_ga. Arrays are row-major, int32 unless stated.
+ *   - `stream` is a hipStream_t (NULL = default stream). Calls are
+ *     asynchronous on it unless documented to synchronise.
+ *   - Calls return FFS_OK (0) or a negative FFS_E_* code and never allocate
+ *     device memory; scratch memory comes from the caller's workspace.
+ *   - An error raised inside a kernel (bad input found on the device) is
+ *     reported by the next synchronising call of the same workspace
+ *     (ffs_status, ffs_prepare, reschedule) as FFS_E_INVAL/FFS_E_INFEASIBLE.
+ *   - Limits of this build: o_max <= 16, g <= 127, n_jobs < 2^24,
+ *     P_jsm and Q_jsm in [1, 65535], Q_max <= 255, n_active <= 4096.
+ *     Larger instances get FFS_E_UNSUPPORTED.
+ */
+#ifndef FFSGA_H
+#define FFSGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFS_OK 0
+#define FFS_E_INVAL (-1)        /* bad shape, not a permutation, plan breaks the rules */
+#define FFS_E_INFEASIBLE (-2)   /* some Q_jsm > Q_max: no op start can ever fit */
+#define FFS_E_WORKSPACE (-3)    /* workspace missing or too small */
+#define FFS_E_DEVICE (-4)       /* HIP runtime error */
+#define FFS_E_UNSUPPORTED (-5)  /* outside the limits of this build */
+
+/* One event's instance (Section 3, Table 2): every job known so far and the
+ * state frozen at the rescheduling point. */
+typedef struct {
+  int32_t n_jobs, n_stages, o_max;  /* |J u J'|, g, row width of proc/power */
+  const int32_t *n_machines;        /* device [g]: o_s, 1 <= o_s <= o_max */
+  const int32_t *proc;              /* device [n_jobs][g][o_max]: P_jsm (m < o_s read) */
+  const int32_t *power;             /* device [n_jobs][g][o_max]: Q_jsm */
+  const int32_t *release, *due;     /* device [n_jobs]: R_j, D_j */
+  int32_t q_max, wt, rs;            /* Q_max, WT, RS (0 for the first plan) */
+  const int32_t *first_stage;       /* device [n_jobs]: first unfrozen stage, g = none */
+  const int32_t *ready;             /* device [n_jobs]: earliest start of that stage */
+  const int32_t *machine_free;      /* device [g][o_max]: end of the last frozen op */
+  int32_t n_running;
+  const int32_t *running;           /* device [n_running][2]: (end, q) of ops running at RS */
+  int64_t frozen_tardiness;         /* sum of T_j over jobs whose every op is frozen */
+  int32_t frozen_cmax;              /* max C_j over those jobs, 0 if none */
+  int32_t n_active;
+  const int32_t *active;            /* device [n_active]: unfrozen jobs; gene k <-> active[k] */
+  int32_t horizon;                  /* host: slots after RS bounding every completion;
+                                       set by ffs_prepare and reschedule */
+} ffs_instance;
+
+/* Workspace bytes any ffs_prepare / ffs_status call needs. */
+#define FFS_PREPARE_WORKSPACE 256
+
+/* Check `inst` on the device (shapes, P/Q ranges, Q_jsm <= Q_max, active list
+ * consistent with first_stage) and set inst->horizon: an upper bound on
+ * (completion - RS) of every op any decode can place. Synchronises `stream`.
+ * workspace: device, >= FFS_PREPARE_WORKSPACE bytes.
+ * Errors: FFS_E_INVAL, FFS_E_INFEASIBLE, FFS_E_UNSUPPORTED, FFS_E_DEVICE. */
+int ffs_prepare(ffs_instance *inst, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Device workspace bytes for ffs_decode of `pop` chromosomes. lds_slots: the
+ * power-profile slots kept on chip per chromosome (0 = library default);
+ * decodes that need more fall back to a slower profile in this workspace. */
+size_t ffs_decode_workspace_size(const ffs_instance *inst, int32_t pop, int32_t lds_slots);
+
+/* Decode pop priority vectors (Section 4.3, Algorithm 2, eq. (1)).
+ * prio: device [pop][n_active], each a permutation of 1..n_active.
+ * obj: device int64 [pop], WT * sum_j T_j + C_max over J u J'.
+ * start, mach: device [pop][n_jobs][g] or NULL: start time and machine of every
+ *   decoded op; entries of frozen ops are not written.
+ * work: device int64 [pop] or NULL: algorithmic operation count of each decode
+ *   (per op: 3*o_s for the machine choice, S - t0 + p slots examined by the
+ *   push-right from its first candidate start t0, p slots updated).
+ * A vector that is not a permutation gets obj = -1 and is reported by
+ * ffs_status. inst must have been through ffs_prepare.
+ * Errors: FFS_E_INVAL, FFS_E_WORKSPACE, FFS_E_UNSUPPORTED, FFS_E_DEVICE. */
+int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
+               int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Read and clear the device-side error flags of a workspace used by
+ * ffs_decode or the GA (any kernel that met a bad input sets them).
+ * Synchronises `stream`. Returns FFS_OK, FFS_E_INVAL or FFS_E_INFEASIBLE. */
+int ffs_status(void *workspace, void *stream);
+
+/* GA parameters (Sections 4.2, 4.4, 5.1). The population is `islands`
+ * islands of rows x cols individuals on a torus, contiguous per island.
+ * pc, pm: crossover / mutation happen when the high 32 bits of a draw are
+ * below the threshold (floor(p * 2^32)). Every mig_interval generations the
+ * mig_k best of island i-1 replace the mig_k worst of island i. */
+typedef struct {
+  int32_t islands, rows, cols;
+  uint32_t pc, pm;
+  int32_t mig_interval, mig_k;
+  int32_t lds_slots;                /* on-chip profile slots per decode, 0 = default */
+} ffs_ga_params;
+
+/* GA state. Filled by ga_init; the caller owns the struct and the workspace.
+ * The device pointers point into the workspace. ga_step must be given the
+ * instance ga_init was given. */
+typedef struct {
+  ffs_ga_params params;
+  int32_t n_genes, pop;
+  uint64_t seed, shop;
+  int32_t event, generation, cur;   /* cur: which of the two population buffers is live */
+  int32_t lds_slots;                /* resolved on-chip profile slots */
+  int32_t n_jobs, horizon;          /* of the instance given to ga_init */
+  void *workspace;
+  size_t workspace_bytes;
+  int32_t *prio[2];                 /* device [pop][n_genes] */
+  int64_t *obj[2];                  /* device [pop] */
+  int32_t *elite;                   /* device [islands][n_genes] */
+  int64_t *elite_obj;               /* device [islands] */
+} ffs_ga;
+
+/* Device views of a GA state (pointers into its workspace). */
+typedef struct {
+  int32_t *prio;       /* [pop][n_genes] */
+  int64_t *obj;        /* [pop] */
+  int32_t *elite;      /* [islands][n_genes]: best-in-history per island */
+  int64_t *elite_obj;  /* [islands] */
+  int64_t *work;       /* [1]: algorithmic work summed over every decode since ga_init
+                          (same count as ffs_decode's work output) */
+} ffs_ga_view;
+
+size_t ffs_ga_workspace_size(const ffs_instance *inst, const ffs_ga_params *params);
+
+/* Generation 0 of one event: random unique priorities (Section 4.3) by a
+ * Fisher-Yates shuffle driven by Philox4x64-10 keyed (seed, shop) with
+ * counter (individual, 0, event, block), decode, elite = each island's best.
+ * Errors: FFS_E_INVAL, FFS_E_WORKSPACE, FFS_E_UNSUPPORTED, FFS_E_DEVICE. */
+int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, uint64_t seed,
+            uint64_t shop, int32_t event, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Run n_generations generations in place (Section 4.4): local selection of the
+ * best of self and four torus neighbours, neighbour-paired single-point
+ * crossover with priority correction, swap mutation, decode, elitist
+ * replacement, ring migration every mig_interval generations.
+ * Errors: FFS_E_INVAL, FFS_E_DEVICE. */
+int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream);
+
+/* Copy the best elite (lowest island on ties) to prio_out (device
+ * [n_genes]) and obj_out (device int64 [1]). */
+int ga_best(const ffs_ga *ga, int32_t *prio_out, int64_t *obj_out, void *stream);
+
+/* Device pointers of the live state (no copy). */
+int ga_view(const ffs_ga *ga, ffs_ga_view *view);
+
+/* Workspace bytes reschedule needs. */
+size_t ffs_reschedule_workspace_size(int32_t n_jobs, int32_t n_new);
+
+/* Predictive-reactive complete rescheduling (Section 4.1, eq. (10)): freeze
+ * every op of the executed plan that started before rs (an op is running at
+ * rs when it started before and ends after, Algorithm 1), append the n_new
+ * arrivals and write the next event's instance into `next`.
+ * prev: a prepared instance; plan_start/plan_mach: device [prev->n_jobs][g],
+ *   the executed plan (start and machine of every op of every job).
+ * new_proc/new_power: device [n_new][g][o_max]; new_release/new_due: device [n_new].
+ * next: caller-filled device pointers with room for n_jobs + n_new jobs
+ *   (proc, power, release, due, first_stage, ready, active), g*o_max
+ *   (machine_free) and g*o_max pairs (running); the n_machines pointer may
+ *   alias prev's. The library writes those arrays and every host field of
+ *   `next`, horizon included. Synchronises `stream`.
+ * Errors: FFS_E_INVAL (rs < prev->rs, plan out of range or not a stage
+ *   prefix before rs), FFS_E_INFEASIBLE, FFS_E_WORKSPACE, FFS_E_DEVICE. */
+int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_t *plan_mach,
+               int32_t rs, int32_t n_new, const int32_t *new_proc, const int32_t *new_power,
+               const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Kernel timing with HIP events around every launch of one kernel family:
+ * 0 = decode (ffs_decode), 1 = GA generation (breed + decode), 2 = GA
+ * replacement, 3 = overflow decode. enable != 0 starts a fresh count;
+ * ffs_timing_read synchronises and returns the summed kernel time and the
+ * number of launches since enable. */
+int ffs_timing_enable(int32_t enable);
+int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches);
+
+const char *ffs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -368,3 +368,42 @@ def reschedule(prev, plan_start, plan_mach, rs, new_proc, new_power, new_release
         "frozen_tardiness": int(out.frozen_tardiness), "frozen_cmax": int(out.frozen_cmax),
         "active": bufs["active"][:out.n_active].copy(),
     }
+
+
+def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, events=None):
+    """The predictive-reactive loop (Section 4.1) on the oracle: for each event,
+    run the GA (generation 0 then `generations`), execute the best elite's
+    plan until the next arrival, freeze and reschedule. Returns one dict per
+    event: best_obj, best_prio, the instance dict and the plan after the event."""
+    inst = initial
+    g = int(initial.n_stages)
+    plan_s = np.full((int(initial.n_jobs), g), -1, np.int32)
+    plan_m = np.full((int(initial.n_jobs), g), -1, np.int32)
+    out = []
+    n_events = 1 + len(arrivals) if events is None else events
+    for e in range(n_events):
+        st = ga_run(inst, ga, seed, shop, e, generations, n_threads)
+        prio, obj = ga_best(st)
+        obj2, s, m, _ = decode(inst, prio, want_schedule=True)
+        assert obj2 == obj
+        for j in np.asarray(inst.active):
+            f = int(np.asarray(inst.first_stage)[j])
+            plan_s[j, f:] = s[j, f:]
+            plan_m[j, f:] = m[j, f:]
+        out.append({"best_obj": obj, "best_prio": prio, "instance": inst,
+                     "plan_start": plan_s.copy(), "plan_mach": plan_m.copy()})
+        if e + 1 < n_events and e < len(arrivals):
+            a = arrivals[e]
+            nxt = reschedule(inst, plan_s, plan_m, a.rs, a.proc, a.power, a.release, a.due)
+            k = len(a.release)
+            plan_s = np.vstack([plan_s, np.full((k, g), -1, np.int32)])
+            plan_m = np.vstack([plan_m, np.full((k, g), -1, np.int32)])
+            inst = _Fields(nxt)
+    return out
+
+
+class _Fields:
+    """Attribute access to an instance dict."""
+
+    def __init__(self, d):
+        self.__dict__.update(d)

@@ -1,0 +1,360 @@
+"""Python binding of libffsga.so (include/ffsga.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. torch supplies device memory (int32/int64/uint8 tensors on cuda)
+and the stream (``torch.cuda.current_stream()``). The library must be built
+(``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffsga.so")
+
+FFS_OK = 0
+FFS_E_INVAL = -1
+FFS_E_INFEASIBLE = -2
+FFS_E_WORKSPACE = -3
+FFS_E_DEVICE = -4
+FFS_E_UNSUPPORTED = -5
+FFS_PREPARE_WORKSPACE = 256
+
+TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+
+
+class FfsInstance(ctypes.Structure):
+    _fields_ = [
+        ("n_jobs", ctypes.c_int32), ("n_stages", ctypes.c_int32), ("o_max", ctypes.c_int32),
+        ("n_machines", _vp), ("proc", _vp), ("power", _vp), ("release", _vp), ("due", _vp),
+        ("q_max", ctypes.c_int32), ("wt", ctypes.c_int32), ("rs", ctypes.c_int32),
+        ("first_stage", _vp), ("ready", _vp), ("machine_free", _vp),
+        ("n_running", ctypes.c_int32), ("running", _vp),
+        ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
+        ("n_active", ctypes.c_int32), ("active", _vp),
+        ("horizon", ctypes.c_int32),
+    ]
+
+
+class FfsGaParams(ctypes.Structure):
+    _fields_ = [
+        ("islands", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+        ("pc", ctypes.c_uint32), ("pm", ctypes.c_uint32),
+        ("mig_interval", ctypes.c_int32), ("mig_k", ctypes.c_int32),
+        ("lds_slots", ctypes.c_int32),
+    ]
+
+
+class FfsGa(ctypes.Structure):
+    _fields_ = [
+        ("params", FfsGaParams),
+        ("n_genes", ctypes.c_int32), ("pop", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("shop", ctypes.c_uint64),
+        ("event", ctypes.c_int32), ("generation", ctypes.c_int32), ("cur", ctypes.c_int32),
+        ("lds_slots", ctypes.c_int32), ("n_jobs", ctypes.c_int32), ("horizon", ctypes.c_int32),
+        ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
+        ("prio", _vp * 2), ("obj", _vp * 2), ("elite", _vp), ("elite_obj", _vp),
+    ]
+
+
+class FfsGaView(ctypes.Structure):
+    _fields_ = [("prio", _vp), ("obj", _vp), ("elite", _vp), ("elite_obj", _vp), ("work", _vp)]
+
+
+_P = ctypes.POINTER
+_lib.ffs_prepare.argtypes = [_P(FfsInstance), _vp, ctypes.c_size_t, _vp]
+_lib.ffs_decode_workspace_size.argtypes = [_P(FfsInstance), ctypes.c_int32, ctypes.c_int32]
+_lib.ffs_decode_workspace_size.restype = ctypes.c_size_t
+_lib.ffs_decode.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                            ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.ffs_status.argtypes = [_vp, _vp]
+_lib.ffs_ga_workspace_size.argtypes = [_P(FfsInstance), _P(FfsGaParams)]
+_lib.ffs_ga_workspace_size.restype = ctypes.c_size_t
+_lib.ga_init.argtypes = [_P(FfsGa), _P(FfsInstance), _P(FfsGaParams), ctypes.c_uint64,
+                         ctypes.c_uint64, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.ga_step.argtypes = [_P(FfsGa), _P(FfsInstance), ctypes.c_int32, _vp]
+_lib.ga_best.argtypes = [_P(FfsGa), _vp, _vp, _vp]
+_lib.ga_view.argtypes = [_P(FfsGa), _P(FfsGaView)]
+_lib.ffs_reschedule_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.ffs_reschedule_workspace_size.restype = ctypes.c_size_t
+_lib.reschedule.argtypes = [_P(FfsInstance), _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                            _vp, _vp, _P(FfsInstance), _vp, ctypes.c_size_t, _vp]
+_lib.ffs_timing_enable.argtypes = [ctypes.c_int32]
+_lib.ffs_timing_read.argtypes = [ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64)]
+_lib.ffs_strerror.argtypes = [ctypes.c_int]
+_lib.ffs_strerror.restype = ctypes.c_char_p
+for _f in ("ffs_prepare", "ffs_decode", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
+           "reschedule", "ffs_timing_enable", "ffs_timing_read"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class FfsError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {ffs_strerror(code)} ({code})")
+        self.code = code
+
+
+def ffs_strerror(code):
+    return _lib.ffs_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != FFS_OK:
+        raise FfsError(rc, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    """Device address of a tensor (None -> NULL)."""
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _i32(x, device):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32)).to(device)
+
+
+class DeviceInstance:
+    """An ffs_instance whose arrays live in torch cuda tensors."""
+
+    def __init__(self, s: FfsInstance, tensors: dict):
+        self.s = s
+        self.t = tensors
+
+    @classmethod
+    def from_host(cls, inst, device="cuda", prepare=True, workspace=None):
+        g, om, n = int(inst.n_stages), int(inst.o_max), int(inst.n_jobs)
+        t = {
+            "n_machines": _i32(inst.n_machines, device),
+            "proc": _i32(np.asarray(inst.proc).reshape(n, g, om), device),
+            "power": _i32(np.asarray(inst.power).reshape(n, g, om), device),
+            "release": _i32(inst.release, device), "due": _i32(inst.due, device),
+            "first_stage": _i32(inst.first_stage, device), "ready": _i32(inst.ready, device),
+            "machine_free": _i32(np.asarray(inst.machine_free).reshape(g, om), device),
+            "running": _i32(np.asarray(inst.running).reshape(-1, 2), device),
+            "active": _i32(inst.active, device),
+        }
+        s = FfsInstance(
+            n, g, om, _dptr(t["n_machines"]), _dptr(t["proc"]), _dptr(t["power"]),
+            _dptr(t["release"]), _dptr(t["due"]), int(inst.q_max), int(inst.wt), int(inst.rs),
+            _dptr(t["first_stage"]), _dptr(t["ready"]), _dptr(t["machine_free"]),
+            int(len(inst.running)), _dptr(t["running"]), int(inst.frozen_tardiness),
+            int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0)
+        d = cls(s, t)
+        if prepare:
+            d.prepare(workspace)
+        return d
+
+    @property
+    def n_active(self):
+        return int(self.s.n_active)
+
+    @property
+    def horizon(self):
+        return int(self.s.horizon)
+
+    def prepare(self, workspace=None):
+        ws = workspace if workspace is not None else torch.empty(
+            FFS_PREPARE_WORKSPACE, dtype=torch.uint8, device=self.t["proc"].device)
+        _check(_lib.ffs_prepare(ctypes.byref(self.s), _dptr(ws), ws.numel(), _stream()),
+               "ffs_prepare")
+
+    def to_host(self) -> dict:
+        """Instance fields as numpy arrays and ints (for checks and tests)."""
+        s = self.s
+        out = {k: v.cpu().numpy() for k, v in self.t.items() if not k.startswith("_")}
+        out["running"] = out["running"][:s.n_running].reshape(-1, 2)
+        out["active"] = out["active"][:s.n_active]
+        for k in ("n_jobs", "n_stages", "o_max", "q_max", "wt", "rs", "frozen_tardiness",
+                  "frozen_cmax", "horizon"):
+            out[k] = int(getattr(s, k))
+        n = out["n_jobs"]
+        for k in ("proc", "power"):
+            out[k] = out[k][:n]
+        for k in ("release", "due", "first_stage", "ready"):
+            out[k] = out[k][:n]
+        return out
+
+
+def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
+               want_schedule: bool = False, want_work: bool = False, workspace=None):
+    """Decode prio [pop, n_active] (int32, cuda). Returns obj (int64 [pop]) or a dict."""
+    s = dinst.s
+    dev = dinst.t["proc"].device
+    prio = prio.to(device=dev, dtype=torch.int32).contiguous()
+    pop = int(prio.shape[0]) if prio.dim() == 2 else 1
+    obj = torch.empty(pop, dtype=torch.int64, device=dev)
+    start = mach = work = None
+    if want_schedule:
+        start = torch.full((pop, s.n_jobs, s.n_stages), -1, dtype=torch.int32, device=dev)
+        mach = torch.full((pop, s.n_jobs, s.n_stages), -1, dtype=torch.int32, device=dev)
+    if want_work:
+        work = torch.empty(pop, dtype=torch.int64, device=dev)
+    need = _lib.ffs_decode_workspace_size(ctypes.byref(s), pop, int(lds_slots))
+    if need == 0:
+        raise FfsError(FFS_E_INVAL, "ffs_decode_workspace_size")
+    ws = workspace if workspace is not None and workspace.numel() >= need else torch.empty(
+        need, dtype=torch.uint8, device=dev)
+    _check(_lib.ffs_decode(ctypes.byref(s), _dptr(prio), pop, _dptr(obj), _dptr(start),
+                           _dptr(mach), _dptr(work), int(lds_slots), _dptr(ws), ws.numel(),
+                           _stream()), "ffs_decode")
+    _check(_lib.ffs_status(_dptr(ws), _stream()), "ffs_decode (device status)")
+    if want_schedule or want_work:
+        return {"obj": obj, "start": start, "mach": mach, "work": work}
+    return obj
+
+
+@dataclass
+class GaConfig:
+    islands: int
+    rows: int
+    cols: int
+    pc: int
+    pm: int
+    mig_interval: int = 10
+    mig_k: int = 1
+    lds_slots: int = 0
+
+    @classmethod
+    def of(cls, ga, lds_slots=0):
+        return cls(ga.islands, ga.rows, ga.cols, ga.pc, ga.pm, ga.mig_interval, ga.mig_k, lds_slots)
+
+    def c(self):
+        return FfsGaParams(self.islands, self.rows, self.cols, self.pc, self.pm, self.mig_interval,
+                           self.mig_k, self.lds_slots)
+
+
+class GA:
+    """One event's island GA on the device (ga_init / ga_step / ga_best / ga_view)."""
+
+    def __init__(self, dinst: DeviceInstance, cfg: GaConfig, seed: int, shop: int, event: int,
+                 workspace=None):
+        self.dinst = dinst
+        self.cfg = cfg
+        self.p = cfg.c()
+        self.ga = FfsGa()
+        dev = dinst.t["proc"].device
+        need = _lib.ffs_ga_workspace_size(ctypes.byref(dinst.s), ctypes.byref(self.p))
+        if need == 0:
+            raise FfsError(FFS_E_INVAL, "ffs_ga_workspace_size")
+        self.ws = workspace if workspace is not None and workspace.numel() >= need else torch.empty(
+            need, dtype=torch.uint8, device=dev)
+        _check(_lib.ga_init(ctypes.byref(self.ga), ctypes.byref(dinst.s), ctypes.byref(self.p),
+                            int(seed), int(shop), int(event), _dptr(self.ws), self.ws.numel(),
+                            _stream()), "ga_init")
+
+    @property
+    def generation(self):
+        return int(self.ga.generation)
+
+    def step(self, n_generations=1):
+        _check(_lib.ga_step(ctypes.byref(self.ga), ctypes.byref(self.dinst.s), int(n_generations),
+                            _stream()), "ga_step")
+
+    def status(self):
+        _check(_lib.ffs_status(_dptr(self.ws), _stream()), "ga (device status)")
+
+    def best(self):
+        n = max(int(self.ga.n_genes), 1)
+        dev = self.ws.device
+        prio = torch.empty(n, dtype=torch.int32, device=dev)
+        obj = torch.empty(1, dtype=torch.int64, device=dev)
+        _check(_lib.ga_best(ctypes.byref(self.ga), _dptr(prio), _dptr(obj), _stream()), "ga_best")
+        return prio[: self.ga.n_genes], obj
+
+    def _slice(self, ptr, count, dtype):
+        off = ptr - self.ws.data_ptr()
+        size = torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off: off + count * size].view(dtype)
+
+    def view(self):
+        """Tensors viewing the live state: prio [pop, n], obj [pop], elite [I, n], elite_obj [I]."""
+        v = FfsGaView()
+        _check(_lib.ga_view(ctypes.byref(self.ga), ctypes.byref(v)), "ga_view")
+        pop, n, isl = int(self.ga.pop), int(self.ga.n_genes), self.cfg.islands
+        return {
+            "prio": self._slice(v.prio, pop * n, torch.int32).view(pop, n),
+            "obj": self._slice(v.obj, pop, torch.int64),
+            "elite": self._slice(v.elite, isl * n, torch.int32).view(isl, n),
+            "elite_obj": self._slice(v.elite_obj, isl, torch.int64),
+            "work": self._slice(v.work, 1, torch.int64),
+        }
+
+
+def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.Tensor, arrival,
+               workspace=None) -> DeviceInstance:
+    """Freeze `prev`'s executed plan at arrival.rs, append the arrival's jobs."""
+    s = prev.s
+    dev = prev.t["proc"].device
+    g, om = int(s.n_stages), int(s.o_max)
+    n_new = int(len(arrival.release))
+    n = int(s.n_jobs) + n_new
+    t = {
+        "n_machines": prev.t["n_machines"],
+        "proc": torch.empty((max(n, 1), g, om), dtype=torch.int32, device=dev),
+        "power": torch.empty((max(n, 1), g, om), dtype=torch.int32, device=dev),
+        "release": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "due": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "first_stage": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "ready": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "machine_free": torch.empty((g, om), dtype=torch.int32, device=dev),
+        "running": torch.empty((max(g * om, 1), 2), dtype=torch.int32, device=dev),
+        "active": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+    }
+    nxt = FfsInstance()
+    for k in ("n_machines", "proc", "power", "release", "due", "first_stage", "ready",
+              "machine_free", "running", "active"):
+        setattr(nxt, k, t[k].data_ptr())
+    new = {
+        "proc": _i32(np.asarray(arrival.proc).reshape(n_new, g, om), dev),
+        "power": _i32(np.asarray(arrival.power).reshape(n_new, g, om), dev),
+        "release": _i32(arrival.release, dev), "due": _i32(arrival.due, dev),
+    }
+    need = _lib.ffs_reschedule_workspace_size(int(s.n_jobs), n_new)
+    ws = workspace if workspace is not None and workspace.numel() >= need else torch.empty(
+        need, dtype=torch.uint8, device=dev)
+    ps = plan_start.to(device=dev, dtype=torch.int32).contiguous()
+    pm = plan_mach.to(device=dev, dtype=torch.int32).contiguous()
+    _check(_lib.reschedule(ctypes.byref(s), _dptr(ps), _dptr(pm), int(arrival.rs), n_new,
+                           _dptr(new["proc"]), _dptr(new["power"]), _dptr(new["release"]),
+                           _dptr(new["due"]), ctypes.byref(nxt), _dptr(ws), ws.numel(),
+                           _stream()), "reschedule")
+    t["_new"] = new
+    return DeviceInstance(nxt, t)
+
+
+def timing_enable(on=True):
+    _check(_lib.ffs_timing_enable(1 if on else 0), "ffs_timing_enable")
+
+
+def timing_read(family):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.ffs_timing_read(int(family), ctypes.byref(ms), ctypes.byref(n)), "ffs_timing_read")
+    return float(ms.value), int(n.value)
+
+
+def exported_symbols():
+    """Names declared in include/ffsga.h that the loaded library exports."""
+    names = []
+    for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_status",
+                 "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
+                 "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
+                 "ffs_timing_read", "ffs_strerror"):
+        if hasattr(_lib, name):
+            names.append(name)
+    return names

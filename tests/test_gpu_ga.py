@@ -1,0 +1,173 @@
+"""GPU island GA (ga_init / ga_step / ga_best through the C ABI) against the oracle.
+
+The Philox stream makes every generation recomputable from its predecessor,
+so GPU and oracle populations, objectives and elites must agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10741_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ffs():
+    import torch
+    from paper_1903_10741_amd import ffsga
+    assert torch.cuda.is_available()
+    return torch, ffsga
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _state(ga):
+    v = ga.view()
+    return {k: t.cpu().numpy() for k, t in v.items() if k != "work"}
+
+
+def _same(a, b, what):
+    for k in ("prio", "obj", "elite", "elite_obj"):
+        assert (np.asarray(a[k]) == np.asarray(b[k])).all(), (what, k)
+
+
+def test_ga_init_matches_oracle():
+    torch, ffsga = _ffs()
+    for cfg in (1, 2):
+        wl = W.CONFIGS[cfg](0)
+        _say("ga_init config", cfg)
+        d = ffsga.DeviceInstance.from_host(wl.initial)
+        ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+        ga.status()
+        want = oracle.ga_init(wl.initial, wl.ga, wl.seed, wl.shop, 0, n_threads=8)
+        _same(_state(ga), want, f"init cfg {cfg}")
+
+
+def test_ga_config1_every_generation():
+    torch, ffsga = _ffs()
+    wl = W.config1(0)
+    _say("config 1, 50 generations, checked every generation")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+    st = oracle.ga_init(wl.initial, wl.ga, wl.seed, wl.shop, 0)
+    for k in range(1, wl.generations + 1):
+        ga.step(1)
+        st = oracle.ga_generation(wl.initial, wl.ga, wl.seed, wl.shop, 0, k, st)
+        _same(_state(ga), st, f"gen {k}")
+    ga.status()
+    prio, obj = ga.best()
+    bp, bo = oracle.ga_best(st)
+    assert int(obj.item()) == bo and (prio.cpu().numpy() == bp).all()
+
+
+def test_ga_config2_first_event_prefix():
+    """Config 2 at full population (32 islands x 8x16): 30 generations, three
+    of them migrating, compared whole."""
+    torch, ffsga = _ffs()
+    wl = W.config2(0)
+    _say("config 2, 30 generations, full population")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+    st = oracle.ga_init(wl.initial, wl.ga, wl.seed, wl.shop, 0, n_threads=8)
+    for k in range(1, 31):
+        st = oracle.ga_generation(wl.initial, wl.ga, wl.seed, wl.shop, 0, k, st, n_threads=8)
+        if k % 10 == 0:
+            ga.step(10)
+            _same(_state(ga), st, f"gen {k}")
+    ga.status()
+
+
+def _chained_check(ga, inst, gacfg, seed, shop, event, islands, ffsga):
+    before = _state(ga)
+    gen = ga.generation + 1
+    ga.step(1)
+    after = _state(ga)
+    sel = np.zeros(gacfg.islands, bool)
+    sel[islands] = True
+    want = oracle.ga_generation(inst, gacfg, seed, shop, event, gen, before, island_sel=sel,
+                                n_threads=8)
+    K = gacfg.rows * gacfg.cols
+    for I in islands:
+        sl = slice(I * K, (I + 1) * K)
+        assert (after["prio"][sl] == want["prio"][sl]).all(), (gen, I)
+        assert (after["obj"][sl] == want["obj"][sl]).all(), (gen, I)
+        assert (after["elite"][I] == want["elite"][I]).all(), (gen, I)
+        assert after["elite_obj"][I] == want["elite_obj"][I], (gen, I)
+
+
+def test_ga_config2_full_event_chained():
+    """Config 2's whole first event (500 generations): sampled islands are
+    recomputed by the oracle from the GPU's own previous generation, at plain
+    and migrating generations across the run."""
+    torch, ffsga = _ffs()
+    wl = W.config2(0)
+    _say("config 2, 500 generations, chained checks")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+    rng = np.random.default_rng(1)
+    for stop in (9, 99, 249, 449, 498):
+        ga.step(stop - ga.generation)
+        _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0,
+                       sorted(rng.choice(32, 3, replace=False)), ffsga)
+    assert ga.generation == 500
+    ga.status()
+
+
+def test_ga_config3_chained_sample():
+    """Config 3 (512 islands x 8x16 = 65536): chained checks of sampled islands
+    at a plain and a migrating generation."""
+    torch, ffsga = _ffs()
+    wl = W.config3(0)
+    _say("config 3, pop 65536, chained checks")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+    want0 = oracle.ga_init(wl.initial, W.GaParams(1, 8, 16), wl.seed, wl.shop, 0, n_threads=8)
+    got0 = _state(ga)
+    assert (got0["prio"][:128] == want0["prio"]).all() and (got0["obj"][:128] == want0["obj"]).all()
+    ga.step(8)
+    _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0, [0, 77, 511], ffsga)   # gen 9
+    _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0, [1, 300], ffsga)       # gen 10
+    ga.status()
+
+
+def test_ga_overflow_tier_in_the_loop():
+    """A GA whose decodes mostly overflow the on-chip profile stays bit-exact."""
+    torch, ffsga = _ffs()
+    wl = W.config1(3)
+    _say("GA with lds_slots = 64 (overflow tier)")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga, lds_slots=64), wl.seed, wl.shop, 0)
+    ga.step(12)
+    ga.status()
+    st = oracle.ga_run(wl.initial, wl.ga, wl.seed, wl.shop, 0, 12)
+    _same(_state(ga), st, "overflow GA")
+
+
+def test_ga_odd_island_shape_and_tiny_genes():
+    """Odd torus sides leave unpaired slots; n_active = 1 and 2 have no or one cut."""
+    torch, ffsga = _ffs()
+    for n, (isl, r, c) in ((1, (2, 3, 5)), (2, (3, 3, 3)), (7, (2, 5, 3))):
+        _say("GA shape", isl, r, c, "genes", n)
+        inst = W.random_instance(n, n_jobs=n, n_stages=2, machines=2, percent=50)
+        gp = W.GaParams(isl, r, c, mig_interval=3, mig_k=2)
+        d = ffsga.DeviceInstance.from_host(inst)
+        ga = ffsga.GA(d, ffsga.GaConfig.of(gp), 11, 4, 2)
+        ga.step(7)
+        ga.status()
+        st = oracle.ga_run(inst, gp, 11, 4, 2, 7)
+        _same(_state(ga), st, f"shape {isl}x{r}x{c} n={n}")
+
+
+def test_ga_is_deterministic():
+    torch, ffsga = _ffs()
+    wl = W.config2(1)
+    _say("GA determinism")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    runs = []
+    for _ in range(2):
+        ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+        ga.step(25)
+        runs.append(_state(ga))
+    _same(runs[0], runs[1], "determinism")
