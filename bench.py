@@ -28,23 +28,20 @@ VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(wl, target_s=15.0):
-    """The CPU oracle (OpenMP over the population) on event 0 of the same workload,
-    for as many generations as fit in about target_s seconds."""
+def cpu_baseline(wl):
+    """The CPU oracle (OpenMP over the population, as the paper's master-slave GA) on one
+    full step of the same workload: every event's GA, executed plan and rescheduling."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    st = oracle.ga_init(wl.initial, wl.ga, wl.seed, wl.shop, 0, n_threads=threads)
-    gens = 0
-    while time.perf_counter() - t0 < target_s and gens < wl.generations:
-        gens += 1
-        st = oracle.ga_generation(wl.initial, wl.ga, wl.seed, wl.shop, 0, gens, st,
-                                  n_threads=threads)
+    out = oracle.run_events(wl.initial, wl.arrivals, wl.ga, wl.generations, wl.seed, wl.shop,
+                            n_threads=threads)
     dt = time.perf_counter() - t0
-    decodes = (1 + gens) * wl.ga.pop
+    decodes = len(out) * ((1 + wl.generations) * wl.ga.pop + 1)
     return {"value": decodes / dt, "unit": "decodes/s", "cores": threads, "kind": "oracle",
-            "sample": f"event 0 of the same workload, generation 0 + {gens} generations of "
-                      f"the 4096-individual island GA ({decodes} decodes, {dt:.1f} s)"}
+            "sample": f"one full step: {len(out)} events x (1 + {wl.generations}) generations x "
+                      f"{wl.ga.pop} individuals + plan decodes ({decodes} decodes, {dt:.1f} s)",
+            "best_obj_per_event": [int(e["best_obj"]) for e in out]}
 
 
 def main():
@@ -55,6 +52,10 @@ def main():
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--generations", type=int, default=None,
+                    help="override generations per event (profiling runs only)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -69,6 +70,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     wl = W.config2(args.seed)
+    if args.generations is not None:
+        wl.generations = args.generations
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         run_workload(wl, lds_slots=args.lds_slots)
@@ -94,6 +103,12 @@ def main():
     work_per_decode = work_res.work / max(work_res.ga_decodes, 1)
 
     value = decodes / elapsed
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "ga_generation_kernel_paper-50x5x3.traffic.json")
+    if os.path.exists(tpath):
+        t = json.load(open(tpath))
+        if t.get("build_id") == ffsga.ffs_build_id():  # counters of this very build only
+            traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
     decodes_per_launch = wl.ga.pop
     achieved = work_per_decode * decodes_per_launch / avg_launch_s / 1e12
@@ -124,10 +139,11 @@ def main():
             "peak": VALU_INT32_PEAK_TOPS,
             "unit": "TOP/s int32",
             "frac": achieved / VALU_INT32_PEAK_TOPS,
-            "traffic": None,
+            "traffic": traffic,
             "work_per_decode": work_per_decode,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": gen_launches,
+            "build_id": ffsga.ffs_build_id(),
         },
     }
     if not args.no_cpu_baseline:

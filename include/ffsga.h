@@ -27,9 +27,9 @@
  *   - An error raised inside a kernel (bad input found on the device) is
  *     reported by the next synchronising call of the same workspace
  *     (ffs_status, ffs_prepare, reschedule) as FFS_E_INVAL/FFS_E_INFEASIBLE.
- *   - Limits of this build: o_max <= 16, g <= 127, n_jobs < 2^24,
- *     P_jsm and Q_jsm in [1, 65535], Q_max <= 255, n_active <= 4096.
- *     Larger instances get FFS_E_UNSUPPORTED.
+ *   - Limits of this build: o_max <= 16, g <= 127, n_jobs < 2^20,
+ *     P_jsm and Q_jsm in [1, 65535], Q_max <= 255, n_active <= 4096,
+ *     RS + horizon < 2^27. Larger instances get FFS_E_UNSUPPORTED.
  */
 #ifndef FFSGA_H
 #define FFSGA_H
@@ -190,15 +190,86 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
                const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
                void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched GA: many independent instances (shops) advanced by the same
+ * launches. The batch has n_slots slots of fixed room; each slot holds one
+ * instance (sizes may differ, within the room) with its own population of
+ * islands x rows x cols individuals, its own Philox key (seed, shop) and its
+ * own generation count, kept on the device so that one generation is the
+ * same launch sequence every time (it is captured once in a hipGraph when
+ * use_graph is set and replayed). Every slot's results are bit-identical to
+ * running its instance alone with ga_init / ga_step.
+ * ------------------------------------------------------------------------ */
+#define FFS_SCHEDULE_CHROMOSOME 0   /* one wave decodes one child */
+#define FFS_SCHEDULE_ISLAND 1       /* one wave breeds, decodes and replaces one island */
+#define FFS_BATCH_MAX_SLOTS 4096
+
+typedef struct {
+  int32_t n_slots;         /* instances held at once, <= FFS_BATCH_MAX_SLOTS */
+  int32_t max_jobs;        /* room per slot: n_jobs */
+  int32_t max_genes;       /* room per slot: n_active */
+  int32_t max_stages;      /* room per slot: g */
+  int32_t o_max;           /* row width of every instance's proc/power, <= 16 */
+  int32_t max_horizon;     /* room per slot: instance horizon (off-chip profile) */
+  ffs_ga_params ga;        /* the same for every slot */
+  int32_t schedule;        /* FFS_SCHEDULE_CHROMOSOME or FFS_SCHEDULE_ISLAND */
+  int32_t blocks;          /* persistent grid size (resident waves), 0 = 8 per CU */
+  int32_t use_graph;       /* capture one generation in a hipGraph and replay it */
+} ffs_batch_params;
+
+typedef struct {
+  ffs_batch_params params;
+  int32_t pop, lds_slots, blocks, omp;
+  void *workspace;
+  size_t workspace_bytes;
+  void *graph, *graph_exec;            /* hipGraph_t / hipGraphExec_t of one generation */
+  void *graph_stream;                  /* the stream the graph was captured on */
+  int32_t active[FFS_BATCH_MAX_SLOTS];     /* host mirror: slot holds an instance */
+  int32_t generation[FFS_BATCH_MAX_SLOTS]; /* host mirror: generations run since ga_batch_set */
+  int32_t n_genes[FFS_BATCH_MAX_SLOTS];    /* host mirror: the slot's n_active */
+} ffs_batch;
+
+size_t ffs_batch_workspace_size(const ffs_batch_params *params);
+
+/* Lay out an empty batch in the caller's workspace (every slot inactive). */
+int ga_batch_create(ffs_batch *b, const ffs_batch_params *params, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* Load a prepared instance into a slot and run its generation 0 (as ga_init).
+ * The instance's device arrays must stay valid while the slot is active.
+ * Errors: FFS_E_INVAL, FFS_E_UNSUPPORTED (instance exceeds the slot's room). */
+int ga_batch_set(ffs_batch *b, int32_t slot, const ffs_instance *inst, uint64_t seed,
+                 uint64_t shop, int32_t event, void *stream);
+
+/* Deactivate a slot (its buffers may then be reused by ga_batch_set). */
+int ga_batch_clear(ffs_batch *b, int32_t slot, void *stream);
+
+/* Every active slot runs n_generations generations. With use_graph the first
+ * call captures one generation on `stream` (which must not be the legacy
+ * default stream) and every later generation replays it. */
+int ga_batch_step(ffs_batch *b, int32_t n_generations, void *stream);
+
+int ga_batch_best(const ffs_batch *b, int32_t slot, int32_t *prio_out, int64_t *obj_out,
+                  void *stream);
+int ga_batch_view(const ffs_batch *b, int32_t slot, ffs_ga_view *view);
+
+/* Release the graph (the workspace stays the caller's). */
+int ga_batch_destroy(ffs_batch *b);
+
 /* Kernel timing with HIP events around every launch of one kernel family:
  * 0 = decode (ffs_decode), 1 = GA generation (breed + decode), 2 = GA
- * replacement, 3 = overflow decode. enable != 0 starts a fresh count;
+ * replacement, 3 = overflow decode, 4 = batched generation (breed + decode,
+ * outside graphs). enable != 0 starts a fresh count;
  * ffs_timing_read synchronises and returns the summed kernel time and the
  * number of launches since enable. */
 int ffs_timing_enable(int32_t enable);
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches);
 
 const char *ffs_strerror(int code);
+
+/* Identity of this build: the first 16 hex digits of the sha256 of the HIP
+ * source and this header it was compiled from. */
+const char *ffs_build_id(void);
 
 #ifdef __cplusplus
 }

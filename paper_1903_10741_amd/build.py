@@ -1,4 +1,5 @@
 """Build libffsga.so (HIP, gfx950) in the package directory."""
+import hashlib
 import os
 import subprocess
 
@@ -15,10 +16,20 @@ HIPCC_FLAGS = [
 ]
 
 
+def build_id() -> str:
+    """First 16 hex digits of sha256 over the HIP source and the ABI header."""
+    h = hashlib.sha256()
+    for path in (SRC, os.path.join(INCLUDE, "ffsga.h")):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-o", tmp, SRC]
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, f'-DFFS_BUILD_ID="{build_id()}"', "-I", INCLUDE, "-o", tmp,
+           SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -44,9 +44,10 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kMaxGenes = 4096;
 constexpr int kMaxStages = 127;
-constexpr int kDefaultLdsSlots = 8192;
+constexpr int kDefaultLdsSlots = 4096;
 constexpr int kFixBlocks = 64;       // overflow decodes in flight at once
 constexpr int kHeaderBytes = 256;
+constexpr int kMaxTime = 1 << 27;    // completion times pack as (time << 4 | machine)
 
 // Device-side status word and small results at the head of every workspace.
 struct Header {
@@ -93,6 +94,9 @@ __device__ __forceinline__ uint32_t draw_below(u64 w, uint32_t n) {
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Lane mask of a predicate across the wave.
+__device__ __forceinline__ u64 ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // ---------------------------------------------------------------------------
 // Instance as the kernels see it.
 // ---------------------------------------------------------------------------
@@ -121,7 +125,7 @@ struct LdsProfile {
   int cap;
   __device__ void clear() const {
     uint32_t *w = (uint32_t *)p;
-    for (int x = __lane_id(); x < cap / 4; x += kWave) w[x] = 0;
+    for (int x = __lane_id(); x < (cap + kWave) / 4; x += kWave) w[x] = 0;
   }
   __device__ uint32_t get(int x) const { return p[x]; }
   __device__ void add(int x, uint32_t q) const {
@@ -136,7 +140,7 @@ struct GlobalProfile {
   int cap;
   __device__ void clear() const {
     uint32_t *w = (uint32_t *)p;
-    for (int x = __lane_id(); x < (cap + 3) / 4; x += kWave)
+    for (int x = __lane_id(); x < (cap + kWave) / 4; x += kWave)
       __hip_atomic_store(w + x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence();
   }
@@ -153,34 +157,103 @@ struct GlobalProfile {
 
 enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 
-// Decode the chromosome in gene[0..n) (LDS) with the profile `prof`.
-// order[] is LDS scratch of n int2. On kDecOk, *obj_out holds eq. (1).
-// Every lane must call this; results are uniform.
-template <int MAXM, class Prof>
-__device__ int decode_core(const DInst &I, const int32_t *gene, int2 *order, const Prof &prof,
-                           int64_t *obj_out, int64_t *work_out, int32_t *start_out,
-                           int32_t *mach_out) {
+// LDS of one wave (one chromosome of n genes; words of a packed P|Q row per op):
+//   gene  [n]        the chromosome (input)
+//   jobs  [n]        by rank: job | first_stage << 24  (correction scratch before decode)
+//   rdy   [n]        by rank: completion of the job's last placed stage
+//   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20)
+//   rec   [n+1][o_s] the current stage's packed P | Q << 16 rows, one word per machine
+//   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
+//                    64 stay zero so a chunk read never needs clamping)
+// gene is free once the ranks are built and holds the stage's end times.
+struct Lds {
+  int32_t *gene, *jobs, *rdy;
+  int2 *op;
+  uint32_t *rec;
+  uint8_t *prof;
+};
+
+__host__ __device__ inline size_t lds_bytes(int n, int cap, int maxm) {
+  return 3 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) +
+         align_up((size_t)4 * maxm * (n + 1), 16) + (cap > 0 ? align_up(cap, 16) + kWave : 0);
+}
+
+__device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n, int maxm) {
+  Lds l;
+  const size_t a = align_up((size_t)4 * n + 4, 16);
+  l.gene = (int32_t *)smem;
+  l.jobs = (int32_t *)(smem + a);
+  l.rdy = (int32_t *)(smem + 2 * a);
+  l.op = (int2 *)(smem + 3 * a);
+  l.rec = (uint32_t *)(smem + 3 * a + align_up((size_t)8 * n + 8, 16));
+  l.prof = (uint8_t *)l.rec + align_up((size_t)4 * maxm * (n + 1), 16);
+  return l;
+}
+
+// Minimum over lanes 0..MAXM-1 of v, left in lane MAXM-1 (DPP quad permutes,
+// then row shifts; lanes outside the row contribute the identity).
+template <int MAXM>
+__device__ __forceinline__ uint32_t machine_min(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0x4E, 0xF, 0xF, false));
+  if (MAXM > 4)
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0x114, 0xF, 0xF, false));
+  if (MAXM > 8)
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0x118, 0xF, 0xF, false));
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_max32(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+
+// Decode the chromosome in l.gene (Section 4.3, Algorithm 2, eq. (1)) with the
+// power profile `prof`. On kDecOk lane 0 has written *obj_out. Every lane
+// calls this; the result is uniform.
+//
+// Per stage, the lanes first gather the stage's ops in decode order (jobs by
+// decreasing priority whose first unfrozen stage is reached) with their
+// earliest start and packed P|Q row. Then each op runs on the whole wave:
+// lane m computes the completion on machine m (its free time lives in lane m)
+// and a DPP minimum over (completion << 4 | m) picks the machine of earliest
+// completion, lowest index on ties; the push-right reads 64 profile slots at
+// once and a ballot marks those that would break the peak; the scalar unit
+// moves the start past the last of them inside the window.
+template <int MAXM, bool PLAN, class Prof>
+__device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64_t *obj_out,
+                           int64_t *work_out, int32_t *start_out, int32_t *mach_out) {
   const int lane = __lane_id();
   const int n = I.n;
-  // Job order: the job of gene k has rank n - prio_k (larger priority first).
-  for (int x = lane; x < n; x += kWave) order[x].x = -1;
+  const u64 below = (1ull << lane) - 1;
+  // Rank of gene k: n - prio_k (larger priority first).
+  for (int x = lane; x < n; x += kWave) l.jobs[x] = -1;
   int bad = 0;
+  __asm__ volatile("" ::: "memory");
   for (int k = lane; k < n; k += kWave) {
-    const int v = gene[k];
-    if (v >= 1 && v <= n) order[n - v].x = k;
+    const int v = l.gene[k];
+    if (v >= 1 && v <= n) l.jobs[n - v] = k;
     else bad = 1;
   }
   __asm__ volatile("" ::: "memory");
   for (int x = lane; x < n; x += kWave) {
-    const int k = order[x].x;
+    const int k = l.jobs[x];
     if (k < 0) {
       bad = 1;
     } else {
       const int j = ld_const(I.active, k);
-      order[x] = make_int2(j | (ld_const(I.first, j) << 24), ld_const(I.ready, j));
+      l.jobs[x] = j | (ld_const(I.first, j) << 24);
+      l.rdy[x] = ld_const(I.ready, j);
     }
   }
-  if (__ballot(bad)) return kDecInval;
+  if (ballot64(bad)) return kDecInval;
 
   // Power held by the ops running at RS, on [RS, end).
   prof.clear();
@@ -194,110 +267,133 @@ __device__ int decode_core(const DInst &I, const int32_t *gene, int2 *order, con
   prof.order();
 
   const int rs = I.rs, cap = prof.cap;
-  int64_t tard = I.frozen_t, work = 0;
-  int cmax = I.frozen_cmax;
+  int64_t work = 0;
+  int32_t *endk = l.gene;  // the genes are no longer needed
   for (int s = 0; s < I.g; ++s) {
     const int os = ld_const(I.nm, s);
-    int fr[MAXM];
+    int fr = lane < os ? ld_const(I.mfree, (size_t)s * I.om + lane) : 0;
+    // The stage's ops, compacted in decode order, plus a spare record so the
+    // op loop can prefetch one past the last.
+    int cnt = 0;
+    for (int b = 0; b < n; b += kWave) {
+      const int x = b + lane;
+      const int jf = x < n ? l.jobs[x] : (127 << 24);
+      const bool live = x < n && (jf >> 24) <= s;
+      const u64 mk = ballot64(live);
+      if (live) {
+        const int k = cnt + __popcll(mk & below);
+        const int j = jf & 0xFFFFFF;
+        l.op[k] = make_int2(max(rs, l.rdy[x]), (int)((uint32_t)j | ((uint32_t)x << 20)));
+        // the packed row is padded to MAXM words: load it whole, keep o_s words
+        const uint4 *row = (const uint4 *)(I.pq + ((size_t)j * I.g + s) * I.omp);
+        uint4 w[MAXM / 4];
 #pragma unroll
-    for (int m = 0; m < MAXM; ++m) fr[m] = m < os ? ld_const(I.mfree, (size_t)s * I.om + m) : 0;
-    for (int x = 0; x < n; ++x) {
-      const int2 pi = order[x];
-      const int jf = uni(pi.x), rdy = uni(pi.y);
-      const int j = jf & 0xFFFFFF;
-      if ((jf >> 24) > s) continue;  // frozen at this stage
-      const int est = max(rs, rdy);
-      const size_t row = ((size_t)j * I.g + s) * I.omp;
-      // Machine of earliest completion, ties to the lowest index. The packed
-      // row is padded to MAXM words, so it is read whole.
-      uint32_t rowv[MAXM];
+        for (int c = 0; c < MAXM / 4; ++c) w[c] = row[c];
 #pragma unroll
-      for (int m = 0; m < MAXM; ++m) rowv[m] = ld_const(I.pq, row + m);
-      int best = INT_MAX, mb = 0, first = 0;
-      uint32_t pq = 0;
-#pragma unroll
-      for (int m = 0; m < MAXM; ++m) {
-        const int a = max(est, fr[m]);
-        const int e = a + (int)(rowv[m] & 0xFFFFu);
-        if (m < os && e < best) {
-          best = e;
-          mb = m;
-          pq = rowv[m];
-          first = a;
+        for (int m = 0; m < MAXM; ++m) {
+          const uint32_t word = m % 4 == 0 ? w[m / 4].x
+                                : m % 4 == 1 ? w[m / 4].y
+                                : m % 4 == 2 ? w[m / 4].z
+                                             : w[m / 4].w;
+          if (m < os) l.rec[k * os + m] = word;
         }
       }
+      cnt += __popcll(mk);
+    }
+    if (lane < os) l.rec[cnt * os + lane] = 0;
+    if (lane == 0) l.op[cnt] = make_int2(0, 0);
+    __asm__ volatile("" ::: "memory");
+    const bool my_machine = lane < os;
+    const uint32_t *recp = l.rec + min(lane, os - 1);
+    const int2 *opp = l.op;
+    int2 o = *opp;
+    uint32_t pqv = *recp;
+    int stage_work = 0;
+    for (int k = 0; k < cnt; ++k) {
+      opp += 1;
+      recp += os;
+      const int2 o_next = *opp;
+      const uint32_t pq_next = *recp;
+      // Machine of earliest completion (ties to the lowest index).
+      const uint32_t key =
+          my_machine ? ((uint32_t)(max(o.x, fr) + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane
+                     : 0xFFFFFFFFu;
+      const uint32_t kmin =
+          (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
+      const int mb = (int)(kmin & 15u);
+      const int e = (int)(kmin >> 4);  // completion on mb ignoring power
+      const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)pqv, mb);
       const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
-      if (q > I.q_max) return kDecInfeasible;
+      // Q > Q_max is rejected by the instance checks; even then the unsigned
+      // threshold below only makes every slot pass, so the loop still ends.
       const uint32_t thr = (uint32_t)(I.q_max - q);
-      // Push right: earliest t >= t0 with every slot of [t, t+p) at most thr.
-      // [t, scan) is known clean; the lanes read [scan, scan+64) and the
-      // window jumps past the last breaking slot inside it.
-      const int t0 = first - rs;
-      int t = t0, scan = t0;
-      while (scan < t + p) {
-        const int xx = scan + lane;
-        const uint32_t v = xx < cap ? prof.get(xx) : 0u;
-        const u64 over = __ballot(v > thr);
-        for (;;) {
-          const int lo = max(t - scan, 0);  // window start inside this chunk
-          if (lo >= kWave) {
-            scan = t;
-            break;
-          }
-          const int hi = min(kWave, t + p - scan);
-          const u64 mask = (hi >= kWave ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
-          const u64 hit = over & mask;
-          if (!hit) {
-            scan += hi;
-            break;
-          }
+      // Push right: the earliest t >= t0 with every slot of [t, t+p) at most
+      // thr. The lanes hold the 64 slots [scan, scan+64); a ballot marks the
+      // window's slots that break the peak and t jumps past the last of them,
+      // re-testing the same chunk; a clean window part that runs off the
+      // chunk moves on to the next 64 slots.
+      const int t0 = e - p - rs;
+      int t = t0, scan = min(t0, cap);
+      uint32_t v = prof.get(scan + lane);
+      for (;;) {
+        const int slot = scan + lane;
+        const u64 hit = ballot64(slot >= t && slot < t + p && v > thr);
+        if (!hit && (t + p <= scan + kWave || scan + kWave >= cap)) break;
+        if (hit) {
           t = scan + (kWave - __clzll(hit));
+        } else {
+          scan += kWave;
+          v = prof.get(scan + lane);
         }
       }
-      if (t + p > cap) return kDecOverflow;
-      for (int b = lane; b < p; b += kWave) prof.add(t + b, (uint32_t)q);
+      // Commit: lanes past the window add 0. A window past the on-chip slots
+      // (found once per stage from the machines' end times) makes this decode
+      // be redone off chip; reads stay in the zero padding and writes are
+      // clamped meanwhile.
+      prof.add(min(t + lane, cap - 1), lane < p ? (uint32_t)q : 0u);
+      if (p > kWave)
+        for (int b = lane + kWave; b < p; b += kWave) prof.add(min(t + b, cap - 1), (uint32_t)q);
       prof.order();
       const int end = t + p + rs;
-#pragma unroll
-      for (int m = 0; m < MAXM; ++m) fr[m] = m == mb ? end : fr[m];
-      if (lane == 0) {
-        order[x].y = end;
-        if (start_out) {
-          start_out[(size_t)j * I.g + s] = t + rs;
-          mach_out[(size_t)j * I.g + s] = mb;
-        }
-      }
-      if (s == I.g - 1) {
-        const int late = end - ld_const(I.due, j);
-        tard += late > 0 ? late : 0;
-        cmax = max(cmax, end);
-      }
-      work += 3 * os + (t - t0) + 2 * p;
+      fr = lane == mb ? end : fr;
+      endk[k] = PLAN ? end | (mb << 27) : end;
+      stage_work += end - e + 2 * p;  // (t - t0) + 2p
+      o = o_next;
+      pqv = pq_next;
     }
+    work += (int64_t)stage_work + 3 * os * cnt;
+    if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
+    __asm__ volatile("" ::: "memory");
+    // Completion times back to the jobs; start and machine of every op.
+    for (int k = lane; k < cnt; k += kWave) {
+      const uint32_t jx = (uint32_t)l.op[k].y;
+      const int e = endk[k];
+      const int end = PLAN ? e & (kMaxTime - 1) : e, mb = PLAN ? e >> 27 : 0;
+      l.rdy[jx >> 20] = end;
+      if (PLAN) {
+        const size_t at = (size_t)(jx & 0xFFFFFu) * I.g + s;
+        start_out[at] = end - (int)(l.rec[k * os + mb] & 0xFFFFu);
+        mach_out[at] = mb;
+      }
+    }
+    __asm__ volatile("" ::: "memory");
   }
+  // Objective, eqs. (1)-(3), over every job in J u J'.
+  int64_t tard = 0;
+  int cmax = 0;
+  for (int x = lane; x < n; x += kWave) {
+    const int c = l.rdy[x];
+    const int late = c - ld_const(I.due, l.jobs[x] & 0xFFFFFF);
+    tard += late > 0 ? late : 0;
+    cmax = max(cmax, c);
+  }
+  tard = wave_sum64(tard);
+  cmax = max(wave_max32(cmax), I.frozen_cmax);
   if (lane == 0) {
-    *obj_out = (int64_t)I.wt * tard + cmax;
+    *obj_out = (int64_t)I.wt * (I.frozen_t + tard) + cmax;
     if (work_out) *work_out = work;
   }
   return kDecOk;
-}
-
-struct Lds {
-  int32_t *gene;
-  int2 *order;
-  uint8_t *prof;
-};
-
-__device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
-  Lds l;
-  l.gene = (int32_t *)smem;
-  l.order = (int2 *)(smem + align_up((size_t)4 * n + 4, 16));
-  l.prof = smem + align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 16, 16);
-  return l;
-}
-
-__host__ __device__ inline size_t lds_bytes(int n, int cap) {
-  return align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 16, 16) + align_up(cap, 16);
 }
 
 __device__ void flag_error(Header *h, int status) {
@@ -324,14 +420,15 @@ __global__ __launch_bounds__(64) void decode_kernel(DInst I, const int32_t *__re
                                                     int cap) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int i = blockIdx.x;
-  Lds l = carve_lds(smem, I.n);
+  Lds l = carve_lds(smem, I.n, MAXM);
   const int32_t *src = prio + (size_t)i * I.n;
   for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];
   __asm__ volatile("" ::: "memory");
   const size_t plan = (size_t)i * I.n_jobs * I.g;
-  const int st = decode_core<MAXM>(I, l.gene, l.order, LdsProfile{l.prof, cap}, obj + i,
-                                   work ? work + i : nullptr, start ? start + plan : nullptr,
-                                   mach ? mach + plan : nullptr);
+  const LdsProfile prof{l.prof, cap};
+  int64_t *w = work ? work + i : nullptr;
+  const int st = start ? decode_core<MAXM, true>(I, l, prof, obj + i, w, start + plan, mach + plan)
+                       : decode_core<MAXM, false>(I, l, prof, obj + i, w, nullptr, nullptr);
   if (st == kDecOk) return;
   if (__lane_id() == 0) obj[i] = -1;
   if (st == kDecOverflow) push_overflow(hdr, ovf_list, i);
@@ -347,7 +444,7 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
                                                       const int32_t *ovf_list, uint8_t *gprof,
                                                       size_t gstride) {
   extern __shared__ __align__(16) uint8_t smem[];
-  Lds l = carve_lds(smem, I.n);
+  Lds l = carve_lds(smem, I.n, MAXM);
   const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const GlobalProfile prof{gprof + gstride * blockIdx.x, I.horizon};
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
@@ -357,8 +454,9 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
     __asm__ volatile("" ::: "memory");
     const size_t plan = (size_t)i * I.n_jobs * I.g;
     int64_t w = 0;
-    const int st = decode_core<MAXM>(I, l.gene, l.order, prof, obj + i, work ? work + i : &w,
-                                     start ? start + plan : nullptr, mach ? mach + plan : nullptr);
+    int64_t *wp = work ? work + i : &w;
+    const int st = start ? decode_core<MAXM, true>(I, l, prof, obj + i, wp, start + plan, mach + plan)
+                         : decode_core<MAXM, false>(I, l, prof, obj + i, wp, nullptr, nullptr);
     if (st == kDecOk && !work && __lane_id() == 0) atomicAdd(&hdr->work, (unsigned long long)w);
     if (st != kDecOk) {
       if (__lane_id() == 0) obj[i] = -1;
@@ -434,7 +532,7 @@ __device__ void correct_lds(int32_t *gene, int n, int32_t *first_pos, int32_t *m
   for (int b = 0; b < n; b += kWave) {
     const int v = b + lane + 1;
     const bool missing = v <= n && first_pos[v] == INT_MAX;
-    const u64 m = __ballot(missing);
+    const u64 m = ballot64(missing);
     if (missing) miss[rank + __popcll(m & below)] = v;
     rank += __popcll(m);
   }
@@ -444,7 +542,7 @@ __device__ void correct_lds(int32_t *gene, int n, int32_t *first_pos, int32_t *m
     const int k = b + lane;
     const int v = k < n ? gene[k] : 1;
     const bool dup = k < n && (v < 1 || v > n || first_pos[v] != k);
-    const u64 m = __ballot(dup);
+    const u64 m = ballot64(dup);
     if (dup) gene[k] = miss[rank + __popcll(m & below)];
     rank += __popcll(m);
   }
@@ -460,16 +558,14 @@ __device__ __forceinline__ int slot_of_block(int b, int K, int islands) {
   return ((t / K) * 8 + xcd) * K + t % K;
 }
 
-template <int MAXM>
-__global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int gen, int cap) {
-  extern __shared__ __align__(16) uint8_t smem[];
+// Build the child of slot i for generation gen in l.gene and store it in
+// A.prio_out: local selection of both parents, neighbour-paired crossover with
+// correction, swap mutation. Every lane calls this.
+__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l) {
   const int lane = __lane_id();
-  const int n = I.n, K = A.rows * A.cols;
-  const int i = slot_of_block(blockIdx.x, K, A.islands);
-  Lds l = carve_lds(smem, n);
-  int32_t *first_pos = (int32_t *)l.order;
-  int32_t *miss = first_pos + (n + 1);
-
+  const int K = A.rows * A.cols;
+  int32_t *first_pos = l.jobs;  // n + 1 words, then n words in rdy: free before the decode
+  int32_t *miss = l.rdy;
   // Pair (Fig. 10 is not available; reading: horizontal neighbours
   // (r,2c)-(r,2c+1) on odd generations, vertical (2r,c)-(2r+1,c) on even).
   const int loc = i % K, r = loc / A.cols, c = loc % A.cols;
@@ -519,27 +615,13 @@ __global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int
   }
   int32_t *dst = A.prio_out + (size_t)i * n;
   for (int k = lane; k < n; k += kWave) dst[k] = l.gene[k];
-  int64_t work = 0;
-  const int st = decode_core<MAXM>(I, l.gene, l.order, LdsProfile{l.prof, cap}, A.obj_out + i,
-                                   &work, nullptr, nullptr);
-  if (st == kDecOk) {
-    if (lane == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
-    return;
-  }
-  if (lane == 0) A.obj_out[i] = -1;
-  if (st == kDecOverflow) push_overflow(A.hdr, A.ovf_list, i);
-  else flag_error(A.hdr, st);
 }
 
-// Generation 0: Fisher-Yates over 1..n, draw d from word d % 4 of block d / 4
-// of purpose 0, then decode.
-template <int MAXM>
-__global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) {
-  extern __shared__ __align__(16) uint8_t smem[];
+// Generation 0 of slot i: Fisher-Yates over 1..n, draw d from word d % 4 of
+// block d / 4 of purpose 0; the result goes to l.gene and A.prio_out.
+__device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
   const int lane = __lane_id();
-  const int n = I.n, i = blockIdx.x;
-  Lds l = carve_lds(smem, n);
-  uint32_t *hi = (uint32_t *)l.order;  // n - 1 high words
+  uint32_t *hi = (uint32_t *)l.op;  // n - 1 high words
   for (int k = lane; k < n; k += kWave) l.gene[k] = k + 1;
   const int n_blocks = (n - 1 + 3) / 4;
   for (int b = lane; b < n_blocks; b += kWave) {
@@ -561,16 +643,42 @@ __global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) 
   __asm__ volatile("" ::: "memory");
   int32_t *dst = A.prio_out + (size_t)i * n;
   for (int k = lane; k < n; k += kWave) dst[k] = l.gene[k];
+}
+
+// Decode l.gene for slot i and record the outcome: the objective, the work
+// count, or an overflow entry `tag` for the off-chip redo.
+template <int MAXM>
+__device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
+                                  int tag) {
   int64_t work = 0;
-  const int st = decode_core<MAXM>(I, l.gene, l.order, LdsProfile{l.prof, cap}, A.obj_out + i,
-                                   &work, nullptr, nullptr);
+  const int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work,
+                                          nullptr, nullptr);
   if (st == kDecOk) {
-    if (lane == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
+    if (__lane_id() == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
     return;
   }
-  if (lane == 0) A.obj_out[i] = -1;
-  if (st == kDecOverflow) push_overflow(A.hdr, A.ovf_list, i);
+  if (__lane_id() == 0) A.obj_out[i] = -1;
+  if (st == kDecOverflow) push_overflow(A.hdr, A.ovf_list, tag);
   else flag_error(A.hdr, st);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int gen, int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int K = A.rows * A.cols;
+  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const Lds l = carve_lds(smem, I.n, MAXM);
+  breed_child(A, I.n, i, gen, l);
+  decode_and_record<MAXM>(I, A, i, cap, l, i);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int i = blockIdx.x;
+  const Lds l = carve_lds(smem, I.n, MAXM);
+  init_child(A, I.n, i, l);
+  decode_and_record<MAXM>(I, A, i, cap, l, i);
 }
 
 // Block-wide (value, index) reductions with the lowest index on ties.
@@ -615,11 +723,9 @@ __device__ void island_arg(const int64_t *obj, int base, int K, const uint8_t *t
 
 // Elitist replacement (Section 4.4): the island's best child refreshes the
 // best-in-history, which then overwrites the island's worst child.
-__global__ __launch_bounds__(256) void replace_kernel(int32_t *prio, int64_t *obj, int32_t *elite,
-                                                      int64_t *elite_obj, int K, int n) {
-  __shared__ int64_t sv[256];
-  __shared__ int si[256];
-  const int I = blockIdx.x, base = I * K;
+__device__ void replace_island(int32_t *prio, int64_t *obj, int32_t *elite, int64_t *elite_obj,
+                               int I, int K, int n, int64_t *sv, int *si) {
+  const int base = I * K;
   int64_t bv, wv;
   int b, w;
   island_arg<false>(obj, base, K, nullptr, sv, si, bv, b);
@@ -634,6 +740,13 @@ __global__ __launch_bounds__(256) void replace_kernel(int32_t *prio, int64_t *ob
   for (int k = threadIdx.x; k < n; k += blockDim.x)
     prio[(size_t)(base + w) * n + k] = elite[(size_t)I * n + k];
   if (threadIdx.x == 0) obj[base + w] = elite_obj[I];
+}
+
+__global__ __launch_bounds__(256) void replace_kernel(int32_t *prio, int64_t *obj, int32_t *elite,
+                                                      int64_t *elite_obj, int K, int n) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  replace_island(prio, obj, elite, elite_obj, blockIdx.x, K, n, sv, si);
 }
 
 __global__ __launch_bounds__(256) void elite_init_kernel(const int32_t *prio, const int64_t *obj,
@@ -654,13 +767,10 @@ __global__ __launch_bounds__(256) void elite_init_kernel(const int32_t *prio, co
 // mig_k best of every island (by objective, then slot), then island i's mig_k
 // worst (by objective descending, then slot) take island i-1's best in order;
 // an immigrant better than the elite becomes the elite.
-__global__ __launch_bounds__(256) void migrate_collect_kernel(const int32_t *prio, const int64_t *obj,
-                                                              int32_t *stage_prio, int64_t *stage_obj,
-                                                              int K, int n, int mig_k) {
-  __shared__ int64_t sv[256];
-  __shared__ int si[256];
-  extern __shared__ uint8_t taken[];
-  const int I = blockIdx.x, base = I * K;
+__device__ void migrate_collect_island(const int32_t *prio, const int64_t *obj,
+                                       int32_t *stage_prio, int64_t *stage_obj, int I, int K,
+                                       int n, int mig_k, uint8_t *taken, int64_t *sv, int *si) {
+  const int base = I * K;
   for (int k = threadIdx.x; k < K; k += blockDim.x) taken[k] = 0;
   __syncthreads();
   for (int r = 0; r < mig_k; ++r) {
@@ -677,15 +787,11 @@ __global__ __launch_bounds__(256) void migrate_collect_kernel(const int32_t *pri
   }
 }
 
-__global__ __launch_bounds__(256) void migrate_apply_kernel(int32_t *prio, int64_t *obj,
-                                                            int32_t *elite, int64_t *elite_obj,
-                                                            const int32_t *stage_prio,
-                                                            const int64_t *stage_obj, int K, int n,
-                                                            int mig_k, int islands) {
-  __shared__ int64_t sv[256];
-  __shared__ int si[256];
-  extern __shared__ uint8_t taken[];
-  const int I = blockIdx.x, base = I * K, src = (I + islands - 1) % islands;
+__device__ void migrate_apply_island(int32_t *prio, int64_t *obj, int32_t *elite,
+                                     int64_t *elite_obj, const int32_t *stage_prio,
+                                     const int64_t *stage_obj, int I, int K, int n, int mig_k,
+                                     int islands, uint8_t *taken, int64_t *sv, int *si) {
+  const int base = I * K, src = (I + islands - 1) % islands;
   for (int k = threadIdx.x; k < K; k += blockDim.x) taken[k] = 0;
   __syncthreads();
   for (int r = 0; r < mig_k; ++r) {
@@ -707,6 +813,27 @@ __global__ __launch_bounds__(256) void migrate_apply_kernel(int32_t *prio, int64
   }
 }
 
+__global__ __launch_bounds__(256) void migrate_collect_kernel(const int32_t *prio, const int64_t *obj,
+                                                              int32_t *stage_prio, int64_t *stage_obj,
+                                                              int K, int n, int mig_k) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  extern __shared__ uint8_t taken[];
+  migrate_collect_island(prio, obj, stage_prio, stage_obj, blockIdx.x, K, n, mig_k, taken, sv, si);
+}
+
+__global__ __launch_bounds__(256) void migrate_apply_kernel(int32_t *prio, int64_t *obj,
+                                                            int32_t *elite, int64_t *elite_obj,
+                                                            const int32_t *stage_prio,
+                                                            const int64_t *stage_obj, int K, int n,
+                                                            int mig_k, int islands) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  extern __shared__ uint8_t taken[];
+  migrate_apply_island(prio, obj, elite, elite_obj, stage_prio, stage_obj, blockIdx.x, K, n, mig_k,
+                       islands, taken, sv, si);
+}
+
 __global__ __launch_bounds__(256) void best_kernel(const int32_t *elite, const int64_t *elite_obj,
                                                    int islands, int n, int32_t *prio_out,
                                                    int64_t *obj_out) {
@@ -722,6 +849,233 @@ __global__ __launch_bounds__(256) void best_kernel(const int32_t *elite, const i
   block_arg<false>(bv, bi, sv, si, bv, bi);
   for (int k = threadIdx.x; k < n; k += blockDim.x) prio_out[k] = elite[(size_t)bi * n + k];
   if (threadIdx.x == 0) *obj_out = bv;
+}
+
+// ---------------------------------------------------------------------------
+// Batched GA: slots of independent instances advanced by the same launches.
+// ---------------------------------------------------------------------------
+struct BatchSlot {
+  DInst I;              // pq points into the slot's region of the workspace
+  int32_t *prio[2];     // generation g lives in prio[g & 1]
+  int64_t *obj[2];
+  int32_t *elite;
+  int64_t *elite_obj;
+  int32_t *stage_prio;
+  int64_t *stage_obj;
+  u64 seed, shop;
+  int32_t event;
+  int32_t gen;          // generations run since the slot was set (advanced on the device)
+  int32_t active;
+  int32_t cap;          // on-chip profile slots of this slot's decodes
+};
+
+struct BatchArgs {
+  BatchSlot *slots;
+  Header *hdr;
+  uint8_t *gprof;       // per persistent block: an off-chip profile of gstride bytes
+  size_t gstride;
+  int32_t n_slots, pop, rows, cols, islands, mig_k, mig_interval;
+  uint32_t pc, pm;
+};
+
+// Read a struct the kernel never writes through the scalar cache, word by word.
+template <class T>
+__device__ __forceinline__ T ld_const_struct(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  typedef __attribute__((address_space(4))) const uint32_t cw;
+  T out;
+  const cw *src = (const cw *)p;
+  uint32_t *dst = (uint32_t *)&out;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
+__device__ __forceinline__ GaDev slot_ga(const BatchSlot &S, const BatchArgs &B, int gen) {
+  GaDev A;
+  A.prio_in = S.prio[(gen - 1) & 1];
+  A.obj_in = S.obj[(gen - 1) & 1];
+  A.prio_out = S.prio[gen & 1];
+  A.obj_out = S.obj[gen & 1];
+  A.elite = S.elite;
+  A.elite_obj = S.elite_obj;
+  A.stage_prio = S.stage_prio;
+  A.stage_obj = S.stage_obj;
+  A.hdr = B.hdr;
+  A.ovf_list = nullptr;
+  A.seed = S.seed;
+  A.shop = S.shop;
+  A.event = S.event;
+  A.rows = B.rows;
+  A.cols = B.cols;
+  A.islands = B.islands;
+  A.mig_k = B.mig_k;
+  A.pc = B.pc;
+  A.pm = B.pm;
+  return A;
+}
+
+// Decode the child in l.gene (already stored in A.prio_out) with the on-chip
+// profile; a decode that outgrows it is redone at once with this block's
+// off-chip profile.
+template <int MAXM>
+__device__ void decode_slot(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
+                            const GlobalProfile &gp) {
+  int64_t work = 0;
+  int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
+                                    nullptr);
+  if (st == kDecOverflow) {
+    const int32_t *src = A.prio_out + (size_t)i * I.n;
+    for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];
+    __asm__ volatile("" ::: "memory");
+    work = 0;
+    st = decode_core<MAXM, false>(I, l, gp, A.obj_out + i, &work, nullptr, nullptr);
+  }
+  if (st == kDecOk) {
+    if (__lane_id() == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
+    return;
+  }
+  if (__lane_id() == 0) A.obj_out[i] = -1;
+  flag_error(A.hdr, st == kDecOverflow ? kDecInval : st);
+}
+
+// (value, index) argmin / argmax over one wave, lowest index on ties.
+template <bool MAX>
+__device__ void wave_arg(int64_t &v, int &idx) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int64_t ov = __shfl_xor(v, d, kWave);
+    const int oi = __shfl_xor(idx, d, kWave);
+    const bool take = MAX ? (ov > v || (ov == v && oi < idx)) : (ov < v || (ov == v && oi < idx));
+    if (take) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// Replacement of island I by one wave (same rule as replace_island).
+__device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
+  const int lane = __lane_id(), base = I * K;
+  int64_t bv = LLONG_MAX, wv = LLONG_MIN;
+  int b = INT_MAX, w = INT_MAX;
+  for (int k = lane; k < K; k += kWave) {
+    const int64_t o = A.obj_out[base + k];
+    if (o < bv) {
+      bv = o;
+      b = k;
+    }
+    if (o > wv) {
+      wv = o;
+      w = k;
+    }
+  }
+  wave_arg<false>(bv, b);
+  wave_arg<true>(wv, w);
+  const int64_t old = A.elite_obj[I];
+  if (bv < old) {
+    for (int k = lane; k < n; k += kWave)
+      A.elite[(size_t)I * n + k] = A.prio_out[(size_t)(base + b) * n + k];
+    if (lane == 0) A.elite_obj[I] = bv;
+  }
+  __asm__ volatile("" ::: "memory");
+  // each lane reads back only the elite words it wrote itself
+  for (int k = lane; k < n; k += kWave)
+    A.prio_out[(size_t)(base + w) * n + k] = A.elite[(size_t)I * n + k];
+  if (lane == 0) A.obj_out[base + w] = bv < old ? bv : old;
+}
+
+// One generation of every active slot. ISLAND: an item is an island (its
+// slots in turn, then its replacement); otherwise an item is one child.
+template <int MAXM, bool ISLAND>
+__global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int K = B.rows * B.cols;
+  const int per_slot = ISLAND ? B.islands : B.pop;
+  const int total = B.n_slots * per_slot;
+  uint8_t *gp_mem = B.gprof + B.gstride * blockIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int d = item / per_slot;
+    const BatchSlot S = ld_const_struct(B.slots + d);
+    if (!S.active) continue;
+    const int gen = S.gen + 1;
+    const GaDev A = slot_ga(S, B, gen);
+    const Lds l = carve_lds(smem, S.I.n, MAXM);
+    const GlobalProfile gp{gp_mem, S.I.horizon};
+    if (ISLAND) {
+      const int isl = item % per_slot;
+      for (int k = 0; k < K; ++k) {
+        breed_child(A, S.I.n, isl * K + k, gen, l);
+        decode_slot<MAXM>(S.I, A, isl * K + k, S.cap, l, gp);
+      }
+      replace_island_wave(A, isl, K, S.I.n);
+    } else {
+      const int i = item % per_slot;
+      breed_child(A, S.I.n, i, gen, l);
+      decode_slot<MAXM>(S.I, A, i, S.cap, l, gp);
+    }
+  }
+}
+
+// Generation 0 of slot d.
+template <int MAXM>
+__global__ __launch_bounds__(64) void batch_init_kernel(BatchArgs B, int d) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BatchSlot S = ld_const_struct(B.slots + d);
+  const GaDev A = slot_ga(S, B, 1);  // generation 0 goes to prio[0]: the "input" side of 1
+  GaDev A0 = A;
+  A0.prio_out = S.prio[0];
+  A0.obj_out = S.obj[0];
+  const Lds l = carve_lds(smem, S.I.n, MAXM);
+  const GlobalProfile gp{B.gprof + B.gstride * blockIdx.x, S.I.horizon};
+  for (int i = blockIdx.x; i < B.pop; i += gridDim.x) {
+    init_child(A0, S.I.n, i, l);
+    decode_slot<MAXM>(S.I, A0, i, S.cap, l, gp);
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_replace_kernel(BatchArgs B) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  const int d = blockIdx.x / B.islands, I = blockIdx.x % B.islands;
+  const BatchSlot S = ld_const_struct(B.slots + d);
+  if (!S.active) return;
+  const int cur = (S.gen + 1) & 1;
+  replace_island(S.prio[cur], S.obj[cur], S.elite, S.elite_obj, I, B.rows * B.cols, S.I.n, sv, si);
+}
+
+__device__ __forceinline__ bool migrates(const BatchArgs &B, int gen) {
+  return B.mig_interval > 0 && B.mig_k > 0 && B.islands > 1 && gen % B.mig_interval == 0;
+}
+
+__global__ __launch_bounds__(256) void batch_migrate_collect_kernel(BatchArgs B) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  extern __shared__ uint8_t taken[];
+  const int d = blockIdx.x / B.islands, I = blockIdx.x % B.islands;
+  const BatchSlot S = ld_const_struct(B.slots + d);
+  if (!S.active || !migrates(B, S.gen + 1)) return;
+  const int cur = (S.gen + 1) & 1;
+  migrate_collect_island(S.prio[cur], S.obj[cur], S.stage_prio, S.stage_obj, I, B.rows * B.cols,
+                         S.I.n, B.mig_k, taken, sv, si);
+}
+
+__global__ __launch_bounds__(256) void batch_migrate_apply_kernel(BatchArgs B) {
+  __shared__ int64_t sv[256];
+  __shared__ int si[256];
+  extern __shared__ uint8_t taken[];
+  const int d = blockIdx.x / B.islands, I = blockIdx.x % B.islands;
+  const BatchSlot S = ld_const_struct(B.slots + d);
+  if (!S.active || !migrates(B, S.gen + 1)) return;
+  const int cur = (S.gen + 1) & 1;
+  migrate_apply_island(S.prio[cur], S.obj[cur], S.elite, S.elite_obj, S.stage_prio, S.stage_obj, I,
+                       B.rows * B.cols, S.I.n, B.mig_k, B.islands, taken, sv, si);
+}
+
+// End of a generation: every active slot has one more.
+__global__ __launch_bounds__(256) void batch_advance_kernel(BatchArgs B) {
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < B.n_slots; d += gridDim.x * blockDim.x)
+    if (B.slots[d].active) B.slots[d].gen += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -958,10 +1312,10 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
 struct Timing {
   std::mutex mu;
   bool on = false;
-  std::vector<hipEvent_t> ev[4];
-  size_t used[4] = {0, 0, 0, 0};
-  double ms[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
+  std::vector<hipEvent_t> ev[5];
+  size_t used[5] = {0, 0, 0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  int64_t launches[5] = {0, 0, 0, 0, 0};
 };
 Timing g_timing;
 constexpr size_t kTimingPairs = 4096;
@@ -1003,15 +1357,15 @@ int max_lds_bytes() {
   return v;
 }
 
-int omp_of(int om) { return om <= 8 ? 8 : 16; }
+int omp_of(int om) { return om <= 4 ? 4 : om <= 8 ? 8 : 16; }
 
 int check_host(const ffs_instance *in) {
   if (!in) return FFS_E_INVAL;
   if (in->n_stages < 1 || in->o_max < 1 || in->n_jobs < 0 || in->n_active < 0 ||
       in->n_active > in->n_jobs || in->n_running < 0 || in->q_max < 1)
     return FFS_E_INVAL;
-  if (in->o_max > 16 || in->n_stages > kMaxStages || in->n_jobs >= (1 << 24) || in->q_max > 255 ||
-      in->n_active > kMaxGenes)
+  if (in->o_max > 16 || in->n_stages > kMaxStages || in->n_jobs >= (1 << 20) || in->q_max > 255 ||
+      in->n_active > kMaxGenes || in->rs < 0 || in->rs >= kMaxTime)
     return FFS_E_UNSUPPORTED;
   if (!in->n_machines || !in->proc || !in->power || !in->due || !in->first_stage || !in->ready ||
       !in->machine_free || (in->n_running && !in->running) || (in->n_active && !in->active))
@@ -1094,12 +1448,12 @@ int run_decode(const ffs_instance *in, const int32_t *prio, int32_t pop, int64_t
                int32_t *start, int32_t *mach, int64_t *work, int cap, const DecodeLayout &L,
                hipStream_t stream) {
   const DInst d = make_dinst(in, L.pq);
-  const size_t shmem = lds_bytes(in->n_active, cap);
+  const size_t shmem = lds_bytes(in->n_active, cap, MAXM);
   hipError_t e = launch(0, decode_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, prio, obj,
                         work, start, mach, L.hdr, L.ovf_list, cap);
   if (e != hipSuccess) return FFS_E_DEVICE;
   if (cap < in->horizon) {
-    e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave), lds_bytes(in->n_active, 0),
+    e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave), lds_bytes(in->n_active, 0, MAXM),
                stream, d, prio, obj, work, start, mach, L.hdr, (const int32_t *)L.ovf_list, L.gprof,
                L.gstride);
     if (e != hipSuccess) return FFS_E_DEVICE;
@@ -1222,7 +1576,7 @@ int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hip
   if (cap >= in->horizon) return FFS_OK;
   const DInst d = make_dinst(in, L.pq);
   hipError_t e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
-                        lds_bytes(in->n_active, 0), stream, d, (const int32_t *)L.prio[buf],
+                        lds_bytes(in->n_active, 0, MAXM), stream, d, (const int32_t *)L.prio[buf],
                         L.obj[buf], (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
                         L.hdr, (const int32_t *)L.ovf_list, L.gprof, L.gstride);
   return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
@@ -1234,7 +1588,7 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
   GaDev A = make_gadev(ga, L, 1);  // generation 0 is written to buffer 0
   const int pop = ga->pop, cap = ga->lds_slots, n = in->n_active;
   const int K = ga->params.rows * ga->params.cols;
-  if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap), stream, d, A,
+  if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap, MAXM), stream, d, A,
              cap) != hipSuccess)
     return FFS_E_DEVICE;
   int rc = ga_overflow<MAXM>(in, L, 0, cap, stream);
@@ -1252,7 +1606,7 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
   const DInst d = make_dinst(in, L.pq);
   const int pop = ga->pop, cap = ga->lds_slots, n = in->n_active;
   const int K = ga->params.rows * ga->params.cols;
-  const size_t shmem = lds_bytes(n, cap);
+  const size_t shmem = lds_bytes(n, cap, MAXM);
   for (int32_t k = 0; k < n_gen; ++k) {
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
@@ -1299,12 +1653,182 @@ void set_lds_limits() {
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
+// ---------------------------------------------------------------------------
+// Batched GA host side.
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+  Header *hdr;
+  BatchSlot *slots;
+  uint8_t *slot_base;
+  size_t slot_stride;
+  size_t off_pq, off_prio[2], off_obj[2], off_elite, off_eobj, off_sprio, off_sobj;
+  uint8_t *gprof;
+  size_t gstride, total;
+};
+
+int device_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+  return v > 0 ? v : 256;
+}
+
+int batch_blocks(const ffs_batch_params *p) { return p->blocks > 0 ? p->blocks : 8 * device_cus(); }
+
+BatchLayout batch_layout(void *ws, const ffs_batch_params *p) {
+  BatchLayout L{};
+  uint8_t *b = (uint8_t *)ws;
+  const size_t pop = (size_t)p->ga.islands * p->ga.rows * p->ga.cols;
+  const size_t n = (size_t)p->max_genes, kk = p->ga.mig_k > 0 ? p->ga.mig_k : 1;
+  size_t off = 0;
+  L.hdr = (Header *)(b + off);
+  off += kHeaderBytes;
+  L.slots = (BatchSlot *)(b + off);
+  off += align_up(sizeof(BatchSlot) * p->n_slots, 256);
+  // one slot's region
+  size_t so = 0;
+  L.off_pq = so;
+  so += align_up((size_t)p->max_jobs * p->max_stages * omp_of(p->o_max) * 4 + 64, 256);
+  for (int k = 0; k < 2; ++k) {
+    L.off_prio[k] = so;
+    so += align_up(pop * n * 4 + 4, 256);
+    L.off_obj[k] = so;
+    so += align_up(pop * 8, 256);
+  }
+  L.off_elite = so;
+  so += align_up((size_t)p->ga.islands * n * 4 + 4, 256);
+  L.off_eobj = so;
+  so += align_up((size_t)p->ga.islands * 8, 256);
+  L.off_sprio = so;
+  so += align_up((size_t)p->ga.islands * kk * n * 4 + 4, 256);
+  L.off_sobj = so;
+  so += align_up((size_t)p->ga.islands * kk * 8, 256);
+  L.slot_stride = so;
+  L.slot_base = b + off;
+  off += so * p->n_slots;
+  L.gstride = align_up((size_t)p->max_horizon + kWave, 256);
+  L.gprof = b + off;
+  off += L.gstride * batch_blocks(p);
+  L.total = off;
+  return L;
+}
+
+int check_batch_params(const ffs_batch_params *p) {
+  if (!p || p->n_slots < 1 || p->max_jobs < 1 || p->max_genes < 1 || p->max_stages < 1 ||
+      p->o_max < 1 || p->max_horizon < 1 || p->blocks < 0 ||
+      (p->schedule != FFS_SCHEDULE_CHROMOSOME && p->schedule != FFS_SCHEDULE_ISLAND))
+    return FFS_E_INVAL;
+  int rc = check_ga_params(&p->ga);
+  if (rc) return rc;
+  if (p->n_slots > FFS_BATCH_MAX_SLOTS || p->o_max > 16 || p->max_genes > kMaxGenes ||
+      p->max_stages > kMaxStages || p->max_jobs >= (1 << 20) || p->max_horizon >= kMaxTime)
+    return FFS_E_UNSUPPORTED;
+  return FFS_OK;
+}
+
+int batch_cap(const ffs_batch_params *p) {
+  int cap = p->ga.lds_slots > 0 ? p->ga.lds_slots : kDefaultLdsSlots;
+  cap = (int)align_up((size_t)(cap < 64 ? 64 : cap), 64);
+  if (cap > (int)align_up((size_t)p->max_horizon, 64)) cap = (int)align_up((size_t)p->max_horizon, 64);
+  return cap;
+}
+
+BatchArgs batch_args(const ffs_batch *b, const BatchLayout &L) {
+  BatchArgs B;
+  B.slots = L.slots;
+  B.hdr = L.hdr;
+  B.gprof = L.gprof;
+  B.gstride = L.gstride;
+  B.n_slots = b->params.n_slots;
+  B.pop = b->pop;
+  B.rows = b->params.ga.rows;
+  B.cols = b->params.ga.cols;
+  B.islands = b->params.ga.islands;
+  B.mig_k = b->params.ga.mig_k;
+  B.mig_interval = b->params.ga.mig_interval;
+  B.pc = b->params.ga.pc;
+  B.pm = b->params.ga.pm;
+  return B;
+}
+
+template <int MAXM>
+int batch_generation_launches(const ffs_batch *b, const BatchArgs &B, hipStream_t s, bool timed) {
+  const ffs_batch_params &p = b->params;
+  const size_t shmem = lds_bytes(p.max_genes, b->lds_slots, MAXM);
+  const int K = p.ga.rows * p.ga.cols;
+  const int isl_total = p.n_slots * p.ga.islands;
+  hipError_t e;
+  if (p.schedule == FFS_SCHEDULE_ISLAND) {
+    e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, true>, dim3(b->blocks), dim3(kWave),
+               shmem, s, B);
+  } else {
+    e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, false>, dim3(b->blocks), dim3(kWave),
+               shmem, s, B);
+    if (e == hipSuccess)
+      e = launch(-1, batch_replace_kernel, dim3(isl_total), dim3(256), 0, s, B);
+  }
+  if (e == hipSuccess && p.ga.mig_interval > 0 && p.ga.mig_k > 0 && p.ga.islands > 1) {
+    e = launch(-1, batch_migrate_collect_kernel, dim3(isl_total), dim3(256), (size_t)K, s, B);
+    if (e == hipSuccess)
+      e = launch(-1, batch_migrate_apply_kernel, dim3(isl_total), dim3(256), (size_t)K, s, B);
+  }
+  if (e == hipSuccess)
+    e = launch(-1, batch_advance_kernel, dim3((p.n_slots + 255) / 256), dim3(256), 0, s, B);
+  return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
+}
+
+int batch_generation_any(const ffs_batch *b, const BatchArgs &B, hipStream_t s, bool timed) {
+  switch (b->omp) {
+    case 4: return batch_generation_launches<4>(b, B, s, timed);
+    case 8: return batch_generation_launches<8>(b, B, s, timed);
+    default: return batch_generation_launches<16>(b, B, s, timed);
+  }
+}
+
+template <int MAXM>
+void set_batch_lds_limits() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const int lim = max_lds_bytes();
+  (void)hipFuncSetAttribute((const void *)batch_generation_kernel<MAXM, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)batch_generation_kernel<MAXM, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)batch_init_kernel<MAXM>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+template <int MAXM>
+int batch_init_launch(const ffs_batch *b, const BatchArgs &B, int slot, const BatchLayout &L,
+                      hipStream_t s) {
+  set_batch_lds_limits<MAXM>();
+  const ffs_batch_params &p = b->params;
+  const size_t shmem = lds_bytes(p.max_genes, b->lds_slots, MAXM);
+  const int grid = b->pop < b->blocks ? b->pop : b->blocks;
+  if (launch(-1, batch_init_kernel<MAXM>, dim3(grid), dim3(kWave), shmem, s, B, slot) != hipSuccess)
+    return FFS_E_DEVICE;
+  uint8_t *base = L.slot_base + L.slot_stride * slot;
+  const int n = b->n_genes[slot];
+  if (launch(-1, elite_init_kernel, dim3(p.ga.islands), dim3(256), 0, s,
+             (const int32_t *)(base + L.off_prio[0]), (const int64_t *)(base + L.off_obj[0]),
+             (int32_t *)(base + L.off_elite), (int64_t *)(base + L.off_eobj),
+             p.ga.rows * p.ga.cols, n) != hipSuccess)
+    return FFS_E_DEVICE;
+  return FFS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+#ifndef FFS_BUILD_ID
+#define FFS_BUILD_ID "unknown"
+#endif
+const char *ffs_build_id(void) { return FFS_BUILD_ID; }
 
 const char *ffs_strerror(int code) {
   switch (code) {
@@ -1332,7 +1856,7 @@ int ffs_prepare(ffs_instance *inst, void *workspace, size_t workspace_bytes, voi
   Header host;
   if ((rc = read_header(h, &host, s))) return rc;
   if ((rc = err_code(host.err))) return rc;
-  if (host.horizon > INT_MAX / 2) return FFS_E_UNSUPPORTED;
+  if (host.horizon + inst->rs >= kMaxTime) return FFS_E_UNSUPPORTED;
   inst->horizon = (int32_t)host.horizon;
   return FFS_OK;
 }
@@ -1353,19 +1877,25 @@ int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64
     return FFS_E_INVAL;
   if (pop == 0) return FFS_OK;
   const int cap = resolve_cap(inst, lds_slots);
-  if (lds_bytes(inst->n_active, cap) > (size_t)max_lds_bytes()) return FFS_E_UNSUPPORTED;
+  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
+    return FFS_E_UNSUPPORTED;
   if (!workspace || workspace_bytes < ffs_decode_workspace_size(inst, pop, lds_slots))
     return FFS_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   DecodeLayout L = decode_layout(workspace, inst, pop, cap);
   if ((rc = clear_header(L.hdr, s))) return rc;
   if ((rc = pack(inst, L.pq, s))) return rc;
-  if (inst->o_max <= 8) {
-    set_lds_limits<8>();
-    return run_decode<8>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+  switch (omp_of(inst->o_max)) {
+    case 4:
+      set_lds_limits<4>();
+      return run_decode<4>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+    case 8:
+      set_lds_limits<8>();
+      return run_decode<8>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+    default:
+      set_lds_limits<16>();
+      return run_decode<16>(inst, prio, pop, obj, start, mach, work, cap, L, s);
   }
-  set_lds_limits<16>();
-  return run_decode<16>(inst, prio, pop, obj, start, mach, work, cap, L, s);
 }
 
 int ffs_status(void *workspace, void *stream) {
@@ -1395,7 +1925,8 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   if (!ga || inst->horizon < 1) return FFS_E_INVAL;
   if ((rc = check_ga_params(params))) return rc;
   const int cap = resolve_cap(inst, params->lds_slots);
-  if (lds_bytes(inst->n_active, cap) > (size_t)max_lds_bytes()) return FFS_E_UNSUPPORTED;
+  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
+    return FFS_E_UNSUPPORTED;
   const size_t need = ffs_ga_workspace_size(inst, params);
   if (!workspace || workspace_bytes < need) return FFS_E_WORKSPACE;
   memset(ga, 0, sizeof(*ga));
@@ -1432,12 +1963,17 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
       return FFS_E_DEVICE;
     return FFS_OK;
   }
-  if (inst->o_max <= 8) {
-    set_lds_limits<8>();
-    return ga_init_impl<8>(ga, inst, L, s);
+  switch (omp_of(inst->o_max)) {
+    case 4:
+      set_lds_limits<4>();
+      return ga_init_impl<4>(ga, inst, L, s);
+    case 8:
+      set_lds_limits<8>();
+      return ga_init_impl<8>(ga, inst, L, s);
+    default:
+      set_lds_limits<16>();
+      return ga_init_impl<16>(ga, inst, L, s);
   }
-  set_lds_limits<16>();
-  return ga_init_impl<16>(ga, inst, L, s);
 }
 
 int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream) {
@@ -1451,8 +1987,11 @@ int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *s
     return FFS_OK;
   }
   hipStream_t s = (hipStream_t)stream;
-  if (inst->o_max <= 8) return ga_step_impl<8>(ga, inst, n_generations, s);
-  return ga_step_impl<16>(ga, inst, n_generations, s);
+  switch (omp_of(inst->o_max)) {
+    case 4: return ga_step_impl<4>(ga, inst, n_generations, s);
+    case 8: return ga_step_impl<8>(ga, inst, n_generations, s);
+    default: return ga_step_impl<16>(ga, inst, n_generations, s);
+  }
 }
 
 int ga_view(const ffs_ga *ga, ffs_ga_view *view) {
@@ -1488,7 +2027,7 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
   if (!next || rs < prev->rs || n_new < 0 || (prev->n_jobs > 0 && (!plan_start || !plan_mach)) ||
       (n_new > 0 && (!new_proc || !new_power || !new_release || !new_due)) || !prev->release)
     return FFS_E_INVAL;
-  if (prev->n_jobs + (int64_t)n_new >= (1 << 24)) return FFS_E_UNSUPPORTED;
+  if (prev->n_jobs + (int64_t)n_new >= (1 << 20) || rs >= kMaxTime) return FFS_E_UNSUPPORTED;
   if (!next->proc || !next->power || !next->release || !next->due || !next->first_stage ||
       !next->ready || !next->machine_free || !next->running || !next->active)
     return FFS_E_INVAL;
@@ -1509,7 +2048,7 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
   Header host;
   if ((rc = read_header(h, &host, s))) return rc;
   if ((rc = err_code(host.err))) return rc;
-  if (host.horizon > INT_MAX / 2) return FFS_E_UNSUPPORTED;
+  if (host.horizon + (int64_t)rs >= kMaxTime) return FFS_E_UNSUPPORTED;
   next->n_jobs = prev->n_jobs + n_new;
   next->n_stages = prev->n_stages;
   next->o_max = prev->o_max;
@@ -1525,10 +2064,195 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
   return check_host(next);
 }
 
+size_t ffs_batch_workspace_size(const ffs_batch_params *params) {
+  if (check_batch_params(params)) return 0;
+  return batch_layout(nullptr, params).total;
+}
+
+int ga_batch_create(ffs_batch *b, const ffs_batch_params *params, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+  if (!b) return FFS_E_INVAL;
+  int rc = check_batch_params(params);
+  if (rc) return rc;
+  const size_t need = ffs_batch_workspace_size(params);
+  if (!workspace || workspace_bytes < need) return FFS_E_WORKSPACE;
+  memset(b, 0, sizeof(*b));
+  b->params = *params;
+  b->pop = params->ga.islands * params->ga.rows * params->ga.cols;
+  b->lds_slots = batch_cap(params);
+  b->blocks = batch_blocks(params);
+  b->omp = omp_of(params->o_max);
+  b->workspace = workspace;
+  b->workspace_bytes = workspace_bytes;
+  if (lds_bytes(params->max_genes, b->lds_slots, b->omp) > (size_t)max_lds_bytes())
+    return FFS_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  BatchLayout L = batch_layout(workspace, params);
+  if ((rc = clear_header(L.hdr, s))) return rc;
+  std::vector<BatchSlot> slots((size_t)params->n_slots);
+  memset(slots.data(), 0, sizeof(BatchSlot) * slots.size());
+  if (hipMemcpyAsync(L.slots, slots.data(), sizeof(BatchSlot) * slots.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FFS_E_DEVICE;
+  return FFS_OK;
+}
+
+int ga_batch_set(ffs_batch *b, int32_t slot, const ffs_instance *inst, uint64_t seed,
+                 uint64_t shop, int32_t event, void *stream) {
+  if (!b || !b->workspace || slot < 0 || slot >= b->params.n_slots) return FFS_E_INVAL;
+  int rc = check_host(inst);
+  if (rc) return rc;
+  if (inst->horizon < 1) return FFS_E_INVAL;
+  const ffs_batch_params &p = b->params;
+  if (inst->n_jobs > p.max_jobs || inst->n_active > p.max_genes || inst->n_stages > p.max_stages ||
+      omp_of(inst->o_max) > b->omp || inst->horizon > p.max_horizon)
+    return FFS_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  BatchLayout L = batch_layout(b->workspace, &p);
+  uint8_t *base = L.slot_base + L.slot_stride * slot;
+  // pack the instance's rows at the batch's row width
+  ffs_instance packed_view = *inst;
+  const int rows = inst->n_jobs * inst->n_stages;
+  if (rows > 0) {
+    const int blocks = (int)((rows * (size_t)b->omp + 255) / 256);
+    if (launch(-1, pack_kernel, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, inst->proc,
+               inst->power, (uint32_t *)(base + L.off_pq), rows, inst->o_max, b->omp) != hipSuccess)
+      return FFS_E_DEVICE;
+  }
+  BatchSlot S;
+  memset(&S, 0, sizeof(S));
+  S.I = make_dinst(&packed_view, (const uint32_t *)(base + L.off_pq));
+  S.I.omp = b->omp;
+  for (int k = 0; k < 2; ++k) {
+    S.prio[k] = (int32_t *)(base + L.off_prio[k]);
+    S.obj[k] = (int64_t *)(base + L.off_obj[k]);
+  }
+  S.elite = (int32_t *)(base + L.off_elite);
+  S.elite_obj = (int64_t *)(base + L.off_eobj);
+  S.stage_prio = (int32_t *)(base + L.off_sprio);
+  S.stage_obj = (int64_t *)(base + L.off_sobj);
+  S.seed = seed;
+  S.shop = shop;
+  S.event = event;
+  S.gen = 0;
+  S.active = 1;
+  const int h = (int)align_up((size_t)inst->horizon, 64);
+  S.cap = b->lds_slots < h ? b->lds_slots : h;
+  if (hipMemcpyAsync(L.slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FFS_E_DEVICE;
+  b->active[slot] = 1;
+  b->generation[slot] = 0;
+  b->n_genes[slot] = inst->n_active;
+  if (inst->n_active == 0) {
+    std::vector<int64_t> o((size_t)b->pop, (int64_t)inst->wt * inst->frozen_tardiness + inst->frozen_cmax);
+    if (hipMemcpyAsync(S.obj[0], o.data(), o.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(S.elite_obj, o.data(), (size_t)p.ga.islands * 8, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FFS_E_DEVICE;
+    return FFS_OK;
+  }
+  const BatchArgs B = batch_args(b, L);
+  switch (b->omp) {
+    case 4: return batch_init_launch<4>(b, B, slot, L, s);
+    case 8: return batch_init_launch<8>(b, B, slot, L, s);
+    default: return batch_init_launch<16>(b, B, slot, L, s);
+  }
+}
+
+int ga_batch_clear(ffs_batch *b, int32_t slot, void *stream) {
+  if (!b || !b->workspace || slot < 0 || slot >= b->params.n_slots) return FFS_E_INVAL;
+  BatchLayout L = batch_layout(b->workspace, &b->params);
+  const int32_t zero = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&L.slots[slot].active, &zero, sizeof(zero), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FFS_E_DEVICE;
+  b->active[slot] = 0;
+  return FFS_OK;
+}
+
+int ga_batch_step(ffs_batch *b, int32_t n_generations, void *stream) {
+  if (!b || !b->workspace || n_generations < 0) return FFS_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  BatchLayout L = batch_layout(b->workspace, &b->params);
+  const BatchArgs B = batch_args(b, L);
+  switch (b->omp) {
+    case 4: set_batch_lds_limits<4>(); break;
+    case 8: set_batch_lds_limits<8>(); break;
+    default: set_batch_lds_limits<16>(); break;
+  }
+  if (b->params.use_graph) {
+    if (!s) return FFS_E_INVAL;  // the legacy default stream cannot be captured
+    if (!b->graph_exec) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ge = nullptr;
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return FFS_E_DEVICE;
+      const int rc = batch_generation_any(b, B, s, false);
+      if (hipStreamEndCapture(s, &g) != hipSuccess || rc) return rc ? rc : FFS_E_DEVICE;
+      if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return FFS_E_DEVICE;
+      }
+      b->graph = g;
+      b->graph_exec = ge;
+      b->graph_stream = s;
+    }
+    for (int32_t k = 0; k < n_generations; ++k)
+      if (hipGraphLaunch((hipGraphExec_t)b->graph_exec, s) != hipSuccess) return FFS_E_DEVICE;
+  } else {
+    for (int32_t k = 0; k < n_generations; ++k) {
+      const int rc = batch_generation_any(b, B, s, true);
+      if (rc) return rc;
+    }
+  }
+  for (int d = 0; d < b->params.n_slots; ++d)
+    if (b->active[d]) b->generation[d] += n_generations;
+  return FFS_OK;
+}
+
+int ga_batch_best(const ffs_batch *b, int32_t slot, int32_t *prio_out, int64_t *obj_out,
+                  void *stream) {
+  if (!b || !b->workspace || slot < 0 || slot >= b->params.n_slots || !b->active[slot] || !obj_out)
+    return FFS_E_INVAL;
+  BatchLayout L = batch_layout(b->workspace, &b->params);
+  uint8_t *base = L.slot_base + L.slot_stride * slot;
+  hipError_t e = launch(-1, best_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream,
+                        (const int32_t *)(base + L.off_elite), (const int64_t *)(base + L.off_eobj),
+                        b->params.ga.islands, b->n_genes[slot], prio_out, obj_out);
+  return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
+}
+
+int ga_batch_view(const ffs_batch *b, int32_t slot, ffs_ga_view *view) {
+  if (!b || !b->workspace || slot < 0 || slot >= b->params.n_slots || !view) return FFS_E_INVAL;
+  BatchLayout L = batch_layout(b->workspace, &b->params);
+  uint8_t *base = L.slot_base + L.slot_stride * slot;
+  const int cur = b->generation[slot] & 1;
+  view->prio = (int32_t *)(base + L.off_prio[cur]);
+  view->obj = (int64_t *)(base + L.off_obj[cur]);
+  view->elite = (int32_t *)(base + L.off_elite);
+  view->elite_obj = (int64_t *)(base + L.off_eobj);
+  view->work = (int64_t *)&L.hdr->work;
+  return FFS_OK;
+}
+
+int ga_batch_destroy(ffs_batch *b) {
+  if (!b) return FFS_E_INVAL;
+  if (b->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy((hipGraph_t)b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+  return FFS_OK;
+}
+
 int ffs_timing_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (enable) {
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 5; ++f) {
       if (g_timing.ev[f].empty()) {
         g_timing.ev[f].resize(2 * kTimingPairs);
         for (auto &e : g_timing.ev[f])
@@ -1544,7 +2268,7 @@ int ffs_timing_enable(int32_t enable) {
 }
 
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches) {
-  if (family < 0 || family > 3 || !total_ms || !launches) return FFS_E_INVAL;
+  if (family < 0 || family > 4 || !total_ms || !launches) return FFS_E_INVAL;
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (!g_timing.ev[family].empty()) {
     drain_family(family, g_timing.used[family]);

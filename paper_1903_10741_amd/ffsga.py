@@ -94,6 +94,8 @@ _lib.ffs_timing_enable.argtypes = [ctypes.c_int32]
 _lib.ffs_timing_read.argtypes = [ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64)]
 _lib.ffs_strerror.argtypes = [ctypes.c_int]
 _lib.ffs_strerror.restype = ctypes.c_char_p
+_lib.ffs_build_id.argtypes = []
+_lib.ffs_build_id.restype = ctypes.c_char_p
 for _f in ("ffs_prepare", "ffs_decode", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
            "reschedule", "ffs_timing_enable", "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -107,6 +109,11 @@ class FfsError(RuntimeError):
 
 def ffs_strerror(code):
     return _lib.ffs_strerror(int(code)).decode()
+
+
+def ffs_build_id():
+    """Hash of the HIP source and ABI header the loaded library was built from."""
+    return _lib.ffs_build_id().decode()
 
 
 def _check(rc, what):
@@ -354,7 +361,9 @@ def exported_symbols():
     for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_status",
                  "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
                  "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
-                 "ffs_timing_read", "ffs_strerror"):
+                 "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",
+                 "ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step",
+                 "ga_batch_best", "ga_batch_view", "ga_batch_destroy"):
         if hasattr(_lib, name):
             names.append(name)
     return names

@@ -107,7 +107,7 @@ def test_ga_config2_full_event_chained():
     d = ffsga.DeviceInstance.from_host(wl.initial)
     ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
     rng = np.random.default_rng(1)
-    for stop in (9, 99, 249, 449, 498):
+    for stop in (9, 99, 249, 449, 499):
         ga.step(stop - ga.generation)
         _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0,
                        sorted(rng.choice(32, 3, replace=False)), ffsga)
