@@ -93,6 +93,12 @@ def _load():
                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
                                       ctypes.c_int32, _i32p, _i64p, _i32p, _i64p,
                                       _i32p, _i64p, _i32p, _i64p, _u8p, ctypes.c_int32]
+    lib.orc_ga_breed.argtypes = [ctypes.POINTER(_Instance), ctypes.POINTER(_GaParams),
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, _i32p, _i64p, _i32p, _u8p]
+    lib.orc_ga_finish.argtypes = [ctypes.POINTER(_Instance), ctypes.POINTER(_GaParams),
+                                  ctypes.c_int32, _i32p, _i64p, _i32p, _i64p, _i32p, _i64p, _u8p,
+                                  ctypes.c_int32]
     lib.orc_crossover.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
     lib.orc_crossover.restype = None
     lib.orc_correct.argtypes = [ctypes.c_int32, _i32p]
@@ -103,7 +109,7 @@ def _load():
                                    ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
                                    ctypes.POINTER(_ReschedOut)]
     for f in ("orc_decode", "orc_decode_pop", "orc_decode_ops", "orc_ga_init",
-              "orc_ga_generation", "orc_reschedule"):
+              "orc_ga_generation", "orc_ga_breed", "orc_ga_finish", "orc_reschedule"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -286,6 +292,49 @@ def ga_generation(inst, ga, seed, shop, event, gen, state, island_sel=None, n_th
                                _ptr(sel, _u8p) if sel is not None else None, int(n_threads))
     _check(rc, "orc_ga_generation")
     return {"prio": prio_out[:, :n].copy(), "obj": obj_out, "elite": elite_out[:, :n].copy(),
+            "elite_obj": eobj_out}
+
+
+def ga_breed(inst, ga, seed, shop, event, gen, variant, state):
+    """Selection, crossover and mutation of generation `gen` with the draws of
+    `variant` (0 = the plain generation's). Returns the children [pop, n]."""
+    lib = _load()
+    p = _Pinned(inst)
+    gp = _gp(ga)
+    pop = gp.islands * gp.rows * gp.cols
+    n = p.n_active
+    nn = max(n, 1)
+    prio_in = _arr(state["prio"]).reshape(pop, n) if n else np.zeros((pop, 1), np.int32)
+    obj_in = _arr(state["obj"], np.int64).reshape(pop)
+    out = np.zeros((pop, nn), np.int32)
+    rc = lib.orc_ga_breed(p.ref(), ctypes.byref(gp), seed, shop, event, gen, int(variant),
+                          _ptr(prio_in), _ptr(obj_in, _i64p), _ptr(out), None)
+    _check(rc, "orc_ga_breed")
+    return out[:, :n].copy()
+
+
+def ga_finish(inst, ga, gen, children, state, n_threads=1):
+    """Decode `children` (the bred generation `gen`), then replacement and
+    migration against `state`'s elites. Returns the new state dict."""
+    lib = _load()
+    p = _Pinned(inst)
+    gp = _gp(ga)
+    pop = gp.islands * gp.rows * gp.cols
+    n = p.n_active
+    nn = max(n, 1)
+    prio = np.zeros((pop, nn), np.int32)
+    prio[:, :n] = _arr(children).reshape(pop, n)
+    obj = np.zeros(pop, np.int64)
+    elite_in = np.zeros((gp.islands, nn), np.int32)
+    elite_in[:, :n] = _arr(state["elite"]).reshape(gp.islands, n)
+    eobj_in = _arr(state["elite_obj"], np.int64).reshape(gp.islands)
+    elite_out = np.zeros((gp.islands, nn), np.int32)
+    eobj_out = np.zeros(gp.islands, np.int64)
+    rc = lib.orc_ga_finish(p.ref(), ctypes.byref(gp), gen, _ptr(prio), _ptr(obj, _i64p),
+                           _ptr(elite_in), _ptr(eobj_in, _i64p), _ptr(elite_out),
+                           _ptr(eobj_out, _i64p), None, int(n_threads))
+    _check(rc, "orc_ga_finish")
+    return {"prio": prio[:, :n].copy(), "obj": obj, "elite": elite_out[:, :n].copy(),
             "elite_obj": eobj_out}
 
 

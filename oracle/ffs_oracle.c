@@ -424,29 +424,31 @@ static int32_t select_winner(const orc_ga_params *gp, const int64_t *obj, int32_
   return w;
 }
 
-int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
-                      uint64_t seed, uint64_t shop, int32_t event, int32_t gen,
-                      const int32_t *prio_in, const int64_t *obj_in,
-                      const int32_t *elite_in, const int64_t *elite_obj_in,
-                      int32_t *prio_out, int64_t *obj_out,
-                      int32_t *elite_out, int64_t *elite_obj_out,
-                      const uint8_t *island_sel, int32_t n_threads) {
-  int rc = check_instance(in);
-  if (rc) return rc;
-  if ((rc = check_ga(in, gp))) return rc;
-  if (gen < 1) return ORC_E_INVAL;
-  const int32_t n = in->n_active, R = gp->rows, C = gp->cols, K = R * C;
+/* Islands whose children must be built: the selected ones, plus their ring
+ * predecessors when generation gen migrates. Caller frees. */
+static uint8_t *needed_islands(const orc_ga_params *gp, int32_t gen, const uint8_t *island_sel) {
   const int32_t I_n = gp->islands;
   const int migrate = gp->mig_interval > 0 && gp->mig_k > 0 && I_n > 1 && gen % gp->mig_interval == 0;
-
-  /* Islands whose children must be built: the selected ones, plus their ring
-   * predecessors when this generation migrates. */
   uint8_t *need = (uint8_t *)calloc((size_t)I_n, 1);
   for (int32_t I = 0; I < I_n; ++I)
     if (!island_sel || island_sel[I]) {
       need[I] = 1;
       if (migrate) need[(I - 1 + I_n) % I_n] = 1;
     }
+  return need;
+}
+
+int orc_ga_breed(const orc_instance *in, const orc_ga_params *gp,
+                 uint64_t seed, uint64_t shop, int32_t event, int32_t gen, int32_t variant,
+                 const int32_t *prio_in, const int64_t *obj_in, int32_t *prio_out,
+                 const uint8_t *island_sel) {
+  int rc = check_instance(in);
+  if (rc) return rc;
+  if ((rc = check_ga(in, gp))) return rc;
+  if (gen < 1 || variant < 0) return ORC_E_INVAL;
+  const int32_t n = in->n_active, R = gp->rows, C = gp->cols, K = R * C;
+  const int32_t I_n = gp->islands;
+  uint8_t *need = needed_islands(gp, gen, island_sel);
 
   for (int32_t I = 0; I < I_n; ++I) {
     if (!need[I]) continue;
@@ -458,7 +460,8 @@ int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
     /* 2. Crossover of neighbour pairs (Fig. 10 lost). Reading: pairs are
      * horizontal ((r,2c),(r,2c+1)) on odd generations and vertical
      * ((2r,c),(2r+1,c)) on even ones; the lower slot draws the decision and
-     * the cut 1 + floor(hi32 * (n-1) / 2^32). */
+     * the cut 1 + floor(hi32 * (n-1) / 2^32). Variant v of the breeding
+     * (the screened generation's v-th candidate) draws from block v. */
     if (n >= 2) {
       int32_t *ta = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
       int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -476,7 +479,7 @@ int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
           b = a + C;
         }
         uint64_t w[4];
-        rng_block(seed, shop, (uint64_t)a, (uint64_t)gen, (uint64_t)event, 1, 0, w);
+        rng_block(seed, shop, (uint64_t)a, (uint64_t)gen, (uint64_t)event, 1, (uint64_t)variant, w);
         if ((uint32_t)(w[0] >> 32) < gp->pc) {
           int32_t cut = 1 + (int32_t)draw_below(w[1], (uint32_t)(n - 1));
           int32_t *pa = prio_out + (int64_t)a * n, *pb = prio_out + (int64_t)b * n;
@@ -490,11 +493,41 @@ int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
       /* 3. Mutation (Fig. 12). */
       for (int32_t i = I * K; i < (I + 1) * K; ++i) {
         uint64_t w[4];
-        rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 2, 0, w);
+        rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 2, (uint64_t)variant, w);
         if ((uint32_t)(w[0] >> 32) < gp->pm) orc_mutate(n, prio_out + (int64_t)i * n, w[1], w[2]);
       }
     }
   }
+  free(need);
+  return ORC_OK;
+}
+
+int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
+                      uint64_t seed, uint64_t shop, int32_t event, int32_t gen,
+                      const int32_t *prio_in, const int64_t *obj_in,
+                      const int32_t *elite_in, const int64_t *elite_obj_in,
+                      int32_t *prio_out, int64_t *obj_out,
+                      int32_t *elite_out, int64_t *elite_obj_out,
+                      const uint8_t *island_sel, int32_t n_threads) {
+  int rc = orc_ga_breed(in, gp, seed, shop, event, gen, 0, prio_in, obj_in, prio_out, island_sel);
+  if (rc) return rc;
+  return orc_ga_finish(in, gp, gen, prio_out, obj_out, elite_in, elite_obj_in, elite_out,
+                       elite_obj_out, island_sel, n_threads);
+}
+
+int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
+                  int32_t *prio_out, int64_t *obj_out,
+                  const int32_t *elite_in, const int64_t *elite_obj_in,
+                  int32_t *elite_out, int64_t *elite_obj_out,
+                  const uint8_t *island_sel, int32_t n_threads) {
+  int rc = check_instance(in);
+  if (rc) return rc;
+  if ((rc = check_ga(in, gp))) return rc;
+  if (gen < 1) return ORC_E_INVAL;
+  const int32_t n = in->n_active, K = gp->rows * gp->cols;
+  const int32_t I_n = gp->islands;
+  const int migrate = gp->mig_interval > 0 && gp->mig_k > 0 && I_n > 1 && gen % gp->mig_interval == 0;
+  uint8_t *need = needed_islands(gp, gen, island_sel);
 
   /* 4. Decode every child of the needed islands, eq. (1). */
   int bad = 0;

@@ -104,6 +104,22 @@ int orc_ga_generation(const orc_instance *in, const orc_ga_params *gp,
                       int32_t *elite_out, int64_t *elite_obj_out,
                       const uint8_t *island_sel, int32_t n_threads);
 
+/* The two halves of orc_ga_generation. orc_ga_breed: selection, crossover +
+ * correction and mutation of the needed islands into prio_out, the random
+ * draws of crossover and mutation taken from block `variant` (0 = the plain
+ * generation's). orc_ga_finish: decode of those children, replacement and
+ * migration, in place on prio_out/obj_out. orc_ga_generation is breed
+ * (variant 0) then finish. */
+int orc_ga_breed(const orc_instance *in, const orc_ga_params *gp,
+                 uint64_t seed, uint64_t shop, int32_t event, int32_t gen, int32_t variant,
+                 const int32_t *prio_in, const int64_t *obj_in, int32_t *prio_out,
+                 const uint8_t *island_sel);
+int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
+                  int32_t *prio_out, int64_t *obj_out,
+                  const int32_t *elite_in, const int64_t *elite_obj_in,
+                  int32_t *elite_out, int64_t *elite_obj_out,
+                  const uint8_t *island_sel, int32_t n_threads);
+
 /* GA building blocks, exposed for the tests. */
 void orc_crossover(int32_t n, const int32_t *a, const int32_t *b, int32_t cut,
                    int32_t *child_a, int32_t *child_b);
