@@ -130,30 +130,59 @@ def forward(p: dict, feats, prio, exact: bool = False) -> dict:
     h2 = np.maximum(a2, 0.0)
     z = h2.mean(axis=1)
     y = z @ p["w3"].astype(np.float64) + float(p["b3"][0])
-    return {"rank": rank, "a1": a1, "h1": h1, "a2": a2, "h2": h2, "z": z, "y": y, "W2": W2}
+    return {"prio": prio, "rank": rank, "a1": a1, "h1": h1, "a2": a2, "h2": h2, "z": z, "y": y,
+            "W2": W2}
 
 
-def forward_bound(p: dict, f: dict) -> np.ndarray:
-    """A bound on |y_float32 - y| per chromosome when layer 2, the pool and
-    the output are summed in float32 in any order (at most one rounding per
-    addition, exact products), with layer 1 and the bf16 roundings identical:
-    |fl(sum x_i) - sum x_i| <= gamma_m sum |x_i|, gamma_m = m u / (1 - m u)."""
-    def gamma(m):
-        return m * U32 / (1 - m * U32)
+def _gamma(m):
+    """gamma_m = m u / (1 - m u): |fl(sum of m+1 terms) - sum| <= gamma_m sum |terms|
+    for any order of float32 additions (one rounding each)."""
+    return m * U32 / (1 - m * U32)
+
+
+def _a2_bound(p: dict, f: dict) -> np.ndarray:
+    """|a2_float32 - a2| for layer 2 summed in float32 (exact bf16 products, bias added)."""
+    h = f["h1"].shape[-1]
+    abs_terms = np.abs(f["h1"]) @ np.abs(f["W2"]) + np.abs(p["b2"].astype(np.float64))
+    return _gamma(h + 1) * abs_terms
+
+
+def forward_bound(p: dict, f: dict, order: str = "pool") -> np.ndarray:
+    """A bound on |y_float32 - y| per chromosome, layer 1 and the bf16 roundings
+    being identical on both sides and every sum taken in float32 in any order.
+
+    order "pool": z = (sum over jobs of h2) / n, then y = b3 + z . w3.
+    order "row":  r_k = h2_k . w3 per job, then y = b3 + (sum over jobs of r_k) / n.
+    Each product and the division by n add one rounding (u |value|)."""
     h = f["h1"].shape[-1]
     n = f["h1"].shape[1]
-    abs_terms = np.abs(f["h1"]) @ np.abs(f["W2"]) + np.abs(p["b2"].astype(np.float64))
-    e_a2 = gamma(h + 1) * abs_terms + U32 * np.abs(f["a2"])
-    e_z = e_a2.mean(axis=1) + gamma(n + 1) * np.abs(f["h2"]).mean(axis=1)
+    e_a2 = _a2_bound(p, f)                               # ReLU is 1-Lipschitz
     w3 = np.abs(p["w3"].astype(np.float64))
-    return e_z @ w3 + gamma(h + 1) * (np.abs(f["z"]) @ w3 + abs(float(p["b3"][0])))
+    b3 = abs(float(p["b3"][0]))
+    if order == "pool":
+        zs = np.abs(f["h2"]).sum(axis=1)                 # sum over jobs, per unit
+        e_z = (e_a2.sum(axis=1) + _gamma(n) * zs) / n + U32 * zs / n
+        terms = np.abs(f["z"]) * w3
+        return e_z @ w3 + (_gamma(h + 1) + U32) * (terms.sum(axis=1) + b3)
+    if order == "row":
+        rows = np.abs(f["h2"]) * w3                      # [B, n, h]
+        e_r = e_a2 @ w3 + (_gamma(h) + U32) * rows.sum(axis=2)
+        rs = np.abs(f["h2"] @ p["w3"].astype(np.float64))
+        ssum = rs.sum(axis=1)
+        e_s = e_r.sum(axis=1) + _gamma(n) * (ssum + e_r.sum(axis=1))
+        return e_s / n + U32 * (ssum + e_s) / n + U32 * (ssum / n + b3 + e_s / n) * 2
+    raise ValueError(order)
 
 
 def loss_and_grad(p: dict, feats, prio, target, exact: bool = False):
     """L = mean (y - target)^2 over the batch and its gradient (dict like p, float64).
 
-    With exact=False the layer-2 output gradient is rounded to bf16 where it
-    multiplies h1 (for dW2) and bf16(W2) (for dH1), as on the matrix cores."""
+    The gradient is that of the network as evaluated by `forward` (with
+    exact=False the bf16 roundings of h1 and W2 are part of the function and
+    pass the gradient straight through), taken in float64 with nothing
+    rounded. The kernels round the layer-2 output gradient to bf16 where it
+    is a matrix-core operand; `grad_bound` states how far that and their
+    float32 sums may move each entry."""
     f = forward(p, feats, prio, exact)
     y = f["y"]
     t = np.asarray(target, dtype=np.float64)
@@ -166,15 +195,84 @@ def loss_and_grad(p: dict, feats, prio, target, exact: bool = False):
     gz = dy[:, None] * p["w3"].astype(np.float64)[None] / n          # dL/dh2 of every row
     dA2 = np.where(f["a2"] > 0, gz[:, None, :], 0.0)
     g["b2"] = dA2.sum(axis=(0, 1))
-    dA2m = dA2 if exact else bf16(dA2.astype(np.float32)).astype(np.float64)
-    g["W2"] = np.einsum("bkh,bko->ho", f["h1"], dA2m)
-    dH1 = dA2m @ f["W2"].T
+    g["W2"] = np.einsum("bkh,bko->ho", f["h1"], dA2)
+    dH1 = dA2 @ f["W2"].T
     dA1 = np.where(f["a1"] > 0, dH1, 0.0)
     g["b1"] = dA1.sum(axis=(0, 1))
     x = np.concatenate([f["rank"].astype(np.float64)[..., None],
                         np.broadcast_to(feats.astype(np.float64)[None], (B, n, 3))], axis=2)
     g["W1"] = np.einsum("bkf,bkh->fh", x, dA1)
+    f.update({"dy": dy, "dA2": dA2, "dA1": dA1, "x": x, "target": t})
     return L, g, f
+
+
+def grad_bound(p: dict, f: dict) -> dict:
+    """Elementwise bounds on |g_gpu - g| for the kernels' evaluation of the
+    gradient of `loss_and_grad` (f is its third result):
+
+      y in float32, pool order (forward_bound); t = fl32(ln obj);
+      dy_b = 2 (y_b - t_b) / B;  D_q = sum of dy_b over the chromosomes b
+      whose gene for job k has value v, q = (k, v);  the layer-2 output
+      gradient of table row q is G_q = mask(a2_q > 0) * fl(D_q * w3 / n),
+      rounded to bf16 (unit roundoff 2^-8) as a matrix-core operand;
+      dW2 = sum_q h1_q^T bf16(G_q), dH1_q = bf16(G_q) bf16(W2)^T,
+      dA1 = mask(a1 > 0) * dH1, db1/dW1/db2/dw3/db3 the matching sums,
+      every sum in float32 in any order.
+
+    A layer-2 mask entry whose a2 lies within its float32 error of zero may
+    differ between the two sides; such entries contribute their whole value
+    to the bound. Layer 1 is bit-identical on both sides, so its mask is too."""
+    ub = 2.0 ** -8
+    B, n, h = f["h1"].shape
+    w3 = p["w3"].astype(np.float64)
+    aw3 = np.abs(w3)
+    e_y = forward_bound(p, f, "pool")
+    t = f["target"]
+    dy = f["dy"]
+    e_dy = 2.0 * (e_y + U32 * np.abs(t)) / B + 2 * U32 * np.abs(dy)
+    out = {}
+    out["b3"] = np.array([e_dy.sum() + _gamma(B) * np.abs(dy).sum()])
+    zs = np.abs(f["h2"]).sum(axis=1)
+    e_z = (_a2_bound(p, f).sum(axis=1) + _gamma(n) * zs) / n + U32 * zs / n
+    out["w3"] = (e_dy @ np.abs(f["z"]) + np.abs(dy) @ e_z
+                 + (_gamma(B) + U32) * (np.abs(dy) @ np.abs(f["z"])))
+    # the table rows (k, v) the batch touches, with D_q and its bound
+    q = np.arange(n)[None, :] * n + (np.asarray(f["prio"], np.int64) - 1)   # [B, n]
+    D = np.zeros(n * n)
+    Dabs = np.zeros(n * n)
+    eD = np.zeros(n * n)
+    np.add.at(D, q.reshape(-1), np.repeat(dy, n))
+    np.add.at(Dabs, q.reshape(-1), np.repeat(np.abs(dy), n))
+    np.add.at(eD, q.reshape(-1), np.repeat(e_dy, n))
+    eD += _gamma(B) * Dabs
+    used = Dabs > 0
+    # per touched row: h1, a2, a2 bound, G and its bound (with uncertain masks)
+    first = np.full(n * n, -1)
+    rows_b, rows_k = np.nonzero(np.ones((B, n), bool))
+    first[q[rows_b, rows_k]] = rows_b * n + rows_k
+    idx = first[used]
+    h1 = f["h1"].reshape(B * n, h)[idx]
+    a2 = f["a2"].reshape(B * n, h)[idx]
+    a1 = f["a1"].reshape(B * n, h)[idx]
+    x = f["x"].reshape(B * n, 4)[idx]
+    e_a2 = _a2_bound(p, f).reshape(B * n, h)[idx]
+    Dq, eDq = D[used][:, None], eD[used][:, None]
+    G = np.where(a2 > 0, Dq * w3[None] / n, 0.0)
+    Gmax = (np.abs(Dq) + eDq) * aw3[None] / n
+    unsure = np.abs(a2) <= e_a2
+    e_G = np.where(unsure, Gmax + np.abs(G), (eDq * aw3[None] / n) + 2 * U32 * np.abs(G))
+    Gabs = np.abs(G) + e_G
+    e_Gb = e_G + ub * Gabs                                         # after the bf16 rounding
+    Q = len(idx)
+    out["b2"] = e_G.sum(axis=0) + _gamma(Q) * Gabs.sum(axis=0)
+    out["W2"] = np.abs(h1).T @ e_Gb + _gamma(Q) * (np.abs(h1).T @ (Gabs + e_Gb))
+    W2 = f["W2"]
+    e_dH1 = e_Gb @ np.abs(W2).T + _gamma(h) * ((Gabs + e_Gb) @ np.abs(W2).T)
+    m1 = (a1 > 0).astype(np.float64)
+    dH1abs = (Gabs + e_Gb) @ np.abs(W2).T
+    out["b1"] = (m1 * e_dH1).sum(axis=0) + _gamma(Q) * (m1 * dH1abs).sum(axis=0)
+    out["W1"] = np.abs(x).T @ (m1 * e_dH1) + (_gamma(Q) + U32) * (np.abs(x).T @ (m1 * dH1abs))
+    return out
 
 
 def adam(theta, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -197,3 +197,80 @@ def test_screened_generation_with_one_variant_is_plain():
     assert (cands[0] == oracle.ga_breed(inst, ga, 3, 1, 0, 3, 0, st)).all()
     assert cands.shape == (4, ga.pop, 11) and scores.shape == (4, ga.pop)
     assert (scores[choice, np.arange(ga.pop)] == scores.min(axis=0)).all()
+
+
+def _f32_sum(terms, axis, order):
+    """Sum along `axis` in float32, one rounding per addition, in index order `order`."""
+    t = np.moveaxis(np.asarray(terms, np.float32), axis, 0)
+    acc = np.zeros(t.shape[1:], np.float32)
+    for i in order:
+        acc = acc + t[i]
+    return acc
+
+
+def test_forward_bound_covers_row_order():
+    inst, feats, prio = _case(13, n=30, B=5)
+    p = S.unflatten(W.surrogate_init(6), S.H)
+    p["b2"] = np.random.default_rng(3).normal(size=S.H).astype(np.float32) * 0.05
+    f = S.forward(p, feats, prio)
+    bound = S.forward_bound(p, f, "row")
+    h2 = np.maximum(f["a2"], 0).astype(np.float32)          # a2 rounded once to float32
+    for rev in (False, True):
+        o_ord = np.arange(S.H)[::-1] if rev else np.arange(S.H)
+        k_ord = np.arange(30)[::-1] if rev else np.arange(30)
+        r = _f32_sum(h2 * p["w3"][None, None], 2, o_ord)      # per-row dot with w3
+        y = np.float32(p["b3"][0]) + _f32_sum(r, 1, k_ord) / np.float32(30)
+        assert (np.abs(y.astype(np.float64) - f["y"]) <= bound).all()
+
+
+def test_grad_bound_covers_float32_table_evaluation():
+    """Evaluate the gradient the way the kernels do (aggregated (job, rank) table,
+    bf16 layer-2 gradient operand, float32 sums) and check every entry against
+    the oracle's float64 gradient within grad_bound."""
+    rng = np.random.default_rng(17)
+    n, B = 9, 64
+    inst = W.random_instance(17, n_jobs=n, n_stages=3, machines=2, p_max=30)
+    feats = S.job_features(inst)
+    prio = W.random_population(17, B, n)
+    p = S.unflatten(W.surrogate_init(9), S.H)
+    p["b1"] = rng.normal(size=S.H).astype(np.float32) * 0.1
+    p["b2"] = rng.normal(size=S.H).astype(np.float32) * 0.05
+    tgt = rng.uniform(11.0, 13.0, size=B)
+    L, g, f = S.loss_and_grad(p, feats, prio, tgt)
+    bnd = S.grad_bound(p, f)
+    # float32 evaluation in table form
+    f32 = np.float32
+    Q = n * n
+    kk, vv = np.divmod(np.arange(Q), n)
+    rank = (vv + 1).astype(f32) / f32(n)
+    a1 = (((p["b1"][None] + feats[kk, 0:1] * p["W1"][1][None]) + feats[kk, 1:2] * p["W1"][2][None])
+          + feats[kk, 2:3] * p["W1"][3][None]) + rank[:, None] * p["W1"][0][None]
+    h1 = S.bf16(np.maximum(a1, f32(0)))
+    W2b = S.bf16(p["W2"])
+    a2 = _f32_sum(h1[:, :, None] * W2b[None], 1, range(S.H)) + p["b2"][None]
+    h2 = np.maximum(a2, f32(0))
+    qi = np.arange(n)[None, :] * n + (prio - 1)
+    z = _f32_sum(h2[qi], 1, range(n)) / f32(n)                       # [B, H]
+    y = f32(p["b3"][0]) + _f32_sum(z * p["w3"][None], 1, range(S.H))
+    t32 = tgt.astype(f32)
+    dy = f32(2) * (y - t32) / f32(B)
+    D = np.zeros(Q, f32)
+    for b in range(B):
+        for k in range(n):
+            D[qi[b, k]] = D[qi[b, k]] + dy[b]
+    G = np.where(a2 > 0, (D[:, None] * p["w3"][None]) / f32(n), f32(0)).astype(f32)
+    Gb = S.bf16(G)
+    gpu = {"b3": np.array([_f32_sum(dy, 0, range(B))]),
+           "w3": _f32_sum(dy[:, None] * z, 0, range(B)),
+           "b2": _f32_sum(G, 0, range(Q)),
+           "W2": _f32_sum(h1[:, :, None] * Gb[:, None, :], 0, range(Q))}
+    dH1 = _f32_sum(Gb[:, None, :] * W2b[None], 2, range(S.H))
+    dA1 = np.where(a1 > 0, dH1, f32(0))
+    x = np.concatenate([rank[:, None], feats[kk]], axis=1).astype(f32)
+    gpu["b1"] = _f32_sum(dA1, 0, range(Q))
+    gpu["W1"] = _f32_sum(x[:, :, None] * dA1[:, None, :], 0, range(Q))
+    for k in g:
+        err = np.abs(gpu[k].astype(np.float64).reshape(g[k].shape) - g[k])
+        assert (err <= bnd[k] + 1e-30).all(), (k, float((err - bnd[k]).max()))
+        rel = np.linalg.norm(err) / max(np.linalg.norm(g[k]), 1e-30)
+        assert rel < 2 ** -6, (k, rel)          # the bound is tight enough to mean something
