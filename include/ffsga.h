@@ -259,7 +259,8 @@ int ga_batch_destroy(ffs_batch *b);
 /* Kernel timing with HIP events around every launch of one kernel family:
  * 0 = decode (ffs_decode), 1 = GA generation (breed + decode), 2 = GA
  * replacement, 3 = overflow decode, 4 = batched generation (breed + decode,
- * outside graphs). enable != 0 starts a fresh count;
+ * outside graphs), 5 = screened generation (ffs_surrogate.h: candidate
+ * breeding + scoring + decode). enable != 0 starts a fresh count;
  * ffs_timing_read synchronises and returns the summed kernel time and the
  * number of launches since enable. */
 int ffs_timing_enable(int32_t enable);

@@ -6,8 +6,9 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libffsga.so")
-SRC = os.path.join(HERE, "csrc", "ffsga.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("ffsga.hip", "surrogate.hip")]
 INCLUDE = os.path.join(ROOT, "include")
+HEADERS = [os.path.join(INCLUDE, f) for f in ("ffsga.h", "ffs_surrogate.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -17,9 +18,9 @@ HIPCC_FLAGS = [
 
 
 def build_id() -> str:
-    """First 16 hex digits of sha256 over the HIP source and the ABI header."""
+    """First 16 hex digits of sha256 over the HIP sources and the ABI headers."""
     h = hashlib.sha256()
-    for path in (SRC, os.path.join(INCLUDE, "ffsga.h")):
+    for path in (*SRCS, *HEADERS):
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -29,7 +30,7 @@ def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, *extra, f'-DFFS_BUILD_ID="{build_id()}"', "-I", INCLUDE, "-o", tmp,
-           SRC]
+           *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

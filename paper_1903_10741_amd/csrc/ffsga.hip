@@ -32,6 +32,7 @@
 #include <mutex>
 #include <vector>
 
+#include "ffs_surrogate.h"
 #include "ffsga.h"
 
 typedef unsigned long long u64;
@@ -558,10 +559,13 @@ __device__ __forceinline__ int slot_of_block(int b, int K, int islands) {
   return ((t / K) * 8 + xcd) * K + t % K;
 }
 
-// Build the child of slot i for generation gen in l.gene and store it in
-// A.prio_out: local selection of both parents, neighbour-paired crossover with
-// correction, swap mutation. Every lane calls this.
-__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l) {
+// Build the child of slot i for generation gen in l.gene (and store it in
+// A.prio_out): local selection of both parents, neighbour-paired crossover
+// with correction, swap mutation. Crossover and mutation draw from Philox
+// block `variant` (0 for the plain generation; the screened generation's
+// candidates use 0..V-1). Every lane calls this.
+__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l, int variant = 0,
+                            bool store = true) {
   const int lane = __lane_id();
   const int K = A.rows * A.cols;
   int32_t *first_pos = l.jobs;  // n + 1 words, then n words in rdy: free before the decode
@@ -585,7 +589,7 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l)
   int cut = n;
   if (lead >= 0 && n >= 2) {
     u64 w[4];
-    philox((u64)lead, (u64)gen, (u64)A.event, 1ull << 32, A.seed, A.shop, w);
+    philox((u64)lead, (u64)gen, (u64)A.event, (1ull << 32) | (u64)variant, A.seed, A.shop, w);
     cross = (uint32_t)(w[0] >> 32) < A.pc;
     cut = 1 + (int)draw_below(w[1], (uint32_t)(n - 1));
   }
@@ -600,7 +604,7 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l)
   }
   if (n >= 2) {  // swap mutation (Fig. 12)
     u64 w[4];
-    philox((u64)i, (u64)gen, (u64)A.event, 2ull << 32, A.seed, A.shop, w);
+    philox((u64)i, (u64)gen, (u64)A.event, (2ull << 32) | (u64)variant, A.seed, A.shop, w);
     if ((uint32_t)(w[0] >> 32) < A.pm) {
       const int x = (int)draw_below(w[1], (uint32_t)n);
       int y = (int)draw_below(w[2], (uint32_t)(n - 1));
@@ -613,6 +617,7 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l)
       __asm__ volatile("" ::: "memory");
     }
   }
+  if (!store) return;
   int32_t *dst = A.prio_out + (size_t)i * n;
   for (int k = lane; k < n; k += kWave) dst[k] = l.gene[k];
 }
@@ -678,6 +683,62 @@ __global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) 
   const int i = blockIdx.x;
   const Lds l = carve_lds(smem, I.n, MAXM);
   init_child(A, I.n, i, l);
+  decode_and_record<MAXM>(I, A, i, cap, l, i);
+}
+
+// Surrogate score of one chromosome (genes 1..n in `gene`, any address
+// space): b3 + (sum over k of table[k][gene[k]-1]) / n, summed as 64 lane
+// partials over k = lane, lane + 64, ... and then an xor butterfly, lane 0's
+// result broadcast. sg_score and the screened generation share this order.
+// A gene outside 1..n makes the score NaN (and reads nothing out of range).
+__device__ __forceinline__ float score_genes(const int32_t *gene, int n, const float *table,
+                                             float b3) {
+  const int lane = __lane_id();
+  float s = 0.f;
+  bool bad = false;
+  for (int k = lane; k < n; k += kWave) {
+    const int v = gene[k];
+    const bool ok = v >= 1 && v <= n;
+    bad |= !ok;
+    s += table[(size_t)k * n + (ok ? v - 1 : 0)];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  s = __shfl(s, 0);
+  if (ballot64(bad)) return __builtin_nanf("");
+  return __fadd_rn(b3, __fdiv_rn(s, (float)n));
+}
+
+__global__ __launch_bounds__(64) void sg_score_kernel(const float *table, const float *theta,
+                                                      int n, const int32_t *prio, float *y) {
+  const float s = score_genes(prio + (size_t)blockIdx.x * n, n, table, theta[FFS_SG_PARAMS - 1]);
+  if (__lane_id() == 0) y[blockIdx.x] = s;
+}
+
+// Screened generation: every cell breeds V candidate children, keeps the one
+// with the lowest surrogate score (lowest v on ties), stores and decodes it.
+template <int MAXM>
+__global__ __launch_bounds__(64) void ga_screened_kernel(DInst I, GaDev A, int gen, int cap,
+                                                         const float *table, const float *theta,
+                                                         int V, float *scores, int32_t *choice) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int K = A.rows * A.cols, pop = K * A.islands;
+  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const Lds l = carve_lds(smem, I.n, MAXM);
+  const float b3 = theta[FFS_SG_PARAMS - 1];
+  int best = 0;
+  float best_s = 0.f;
+  for (int v = 0; v < V; ++v) {
+    breed_child(A, I.n, i, gen, l, v, false);
+    const float sv = score_genes(l.gene, I.n, table, b3);
+    if (scores && __lane_id() == 0) scores[(size_t)v * pop + i] = sv;
+    if (v == 0 || sv < best_s) {
+      best_s = sv;
+      best = v;
+    }
+    __asm__ volatile("" ::: "memory");
+  }
+  if (choice && __lane_id() == 0) choice[i] = best;
+  breed_child(A, I.n, i, gen, l, best, true);
   decode_and_record<MAXM>(I, A, i, cap, l, i);
 }
 
@@ -1309,13 +1370,14 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
+constexpr int kTimingFamilies = 6;
 struct Timing {
   std::mutex mu;
   bool on = false;
-  std::vector<hipEvent_t> ev[5];
-  size_t used[5] = {0, 0, 0, 0, 0};
-  double ms[5] = {0, 0, 0, 0, 0};
-  int64_t launches[5] = {0, 0, 0, 0, 0};
+  std::vector<hipEvent_t> ev[kTimingFamilies];
+  size_t used[kTimingFamilies] = {};
+  double ms[kTimingFamilies] = {};
+  int64_t launches[kTimingFamilies] = {};
 };
 Timing g_timing;
 constexpr size_t kTimingPairs = 4096;
@@ -1600,8 +1662,17 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
   return FFS_OK;
 }
 
+// A screened generation's surrogate inputs (ffs_surrogate.h).
+struct Screen {
+  const float *table, *theta;
+  int variants;
+  float *scores;
+  int32_t *choice;
+};
+
 template <int MAXM>
-int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t stream) {
+int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t stream,
+                 const Screen *scr = nullptr) {
   GaLayout L = ga_layout(ga->workspace, in, &ga->params, ga->lds_slots);
   const DInst d = make_dinst(in, L.pq);
   const int pop = ga->pop, cap = ga->lds_slots, n = in->n_active;
@@ -1611,9 +1682,14 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
     GaDev A = make_gadev(ga, L, cur);
-    if (launch(1, ga_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen,
-               cap) != hipSuccess)
-      return FFS_E_DEVICE;
+    hipError_t e;
+    if (scr)
+      e = launch(5, ga_screened_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen, cap,
+                 scr->table, scr->theta, scr->variants, scr->scores, scr->choice);
+    else
+      e = launch(1, ga_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen,
+                 cap);
+    if (e != hipSuccess) return FFS_E_DEVICE;
     int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream);
     if (rc) return rc;
     if (launch(2, replace_kernel, dim3(ga->params.islands), dim3(256), 0, stream, L.prio[1 - cur],
@@ -1650,6 +1726,8 @@ void set_lds_limits() {
   (void)hipFuncSetAttribute((const void *)ga_generation_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void *)ga_init_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)ga_screened_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
@@ -1994,6 +2072,40 @@ int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *s
   }
 }
 
+int sg_score(const ffs_surrogate *model, const float *table, int32_t n_genes, const int32_t *prio,
+             int32_t count, float *y, void *stream) {
+  if (!model || !model->theta || !table || !prio || !y || n_genes < 1 ||
+      n_genes > FFS_SG_MAX_GENES || count < 0)
+    return FFS_E_INVAL;
+  if (launch(-1, sg_score_kernel, dim3(count), dim3(kWave), 0, (hipStream_t)stream, table,
+             (const float *)model->theta, n_genes, prio, y) != hipSuccess)
+    return FFS_E_DEVICE;
+  return FFS_OK;
+}
+
+int ga_step_screened(ffs_ga *ga, const ffs_instance *inst, const ffs_surrogate *model,
+                     const float *table, int32_t variants, int32_t n_generations, float *scores,
+                     int32_t *choice, void *stream) {
+  int rc = check_host(inst);
+  if (rc) return rc;
+  if (!ga || !ga->workspace || n_generations < 0 || inst->n_active != ga->n_genes ||
+      inst->n_jobs != ga->n_jobs || inst->horizon != ga->horizon || !model || !model->theta ||
+      !table || variants < 1 || variants > FFS_SG_MAX_VARIANTS ||
+      inst->n_active > FFS_SG_MAX_GENES)
+    return FFS_E_INVAL;
+  if (inst->n_active == 0) {
+    ga->generation += n_generations;
+    return FFS_OK;
+  }
+  const Screen scr{table, model->theta, variants, scores, choice};
+  hipStream_t s = (hipStream_t)stream;
+  switch (omp_of(inst->o_max)) {
+    case 4: return ga_step_impl<4>(ga, inst, n_generations, s, &scr);
+    case 8: return ga_step_impl<8>(ga, inst, n_generations, s, &scr);
+    default: return ga_step_impl<16>(ga, inst, n_generations, s, &scr);
+  }
+}
+
 int ga_view(const ffs_ga *ga, ffs_ga_view *view) {
   if (!ga || !view || !ga->workspace) return FFS_E_INVAL;
   view->prio = ga->prio[ga->cur];
@@ -2252,7 +2364,7 @@ int ga_batch_destroy(ffs_batch *b) {
 int ffs_timing_enable(int32_t enable) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (enable) {
-    for (int f = 0; f < 5; ++f) {
+    for (int f = 0; f < kTimingFamilies; ++f) {
       if (g_timing.ev[f].empty()) {
         g_timing.ev[f].resize(2 * kTimingPairs);
         for (auto &e : g_timing.ev[f])
@@ -2268,7 +2380,7 @@ int ffs_timing_enable(int32_t enable) {
 }
 
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches) {
-  if (family < 0 || family > 4 || !total_ms || !launches) return FFS_E_INVAL;
+  if (family < 0 || family >= kTimingFamilies || !total_ms || !launches) return FFS_E_INVAL;
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (!g_timing.ev[family].empty()) {
     drain_family(family, g_timing.used[family]);

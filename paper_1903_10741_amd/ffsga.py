@@ -26,6 +26,7 @@ FFS_E_UNSUPPORTED = -5
 FFS_PREPARE_WORKSPACE = 256
 
 TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
+TIMING_BATCH, TIMING_SCREENED = 4, 5
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
@@ -272,6 +273,16 @@ class GA:
         _check(_lib.ga_step(ctypes.byref(self.ga), ctypes.byref(self.dinst.s), int(n_generations),
                             _stream()), "ga_step")
 
+    def step_screened(self, model: "Surrogate", table: torch.Tensor, variants: int = 4,
+                      n_generations: int = 1, scores: torch.Tensor = None,
+                      choice: torch.Tensor = None):
+        """Screened generations (ga_step_screened): `variants` candidates per cell,
+        the lowest surrogate score kept and decoded exactly."""
+        _check(_lib.ga_step_screened(ctypes.byref(self.ga), ctypes.byref(self.dinst.s),
+                                     ctypes.byref(model.s), _dptr(table), int(variants),
+                                     int(n_generations), _dptr(scores), _dptr(choice), _stream()),
+               "ga_step_screened")
+
     def status(self):
         _check(_lib.ffs_status(_dptr(self.ws), _stream()), "ga (device status)")
 
@@ -363,7 +374,279 @@ def exported_symbols():
                  "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
                  "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",
                  "ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step",
-                 "ga_batch_best", "ga_batch_view", "ga_batch_destroy"):
+                 "ga_batch_best", "ga_batch_view", "ga_batch_destroy", "sg_refresh",
+                 "sg_features", "sg_table_workspace_size", "sg_score_table", "sg_score",
+                 "sg_train_workspace_size", "sg_train_step", "ga_step_screened"):
         if hasattr(_lib, name):
             names.append(name)
     return names
+
+
+# --------------------------------------------------------------------------
+# Batched GA (ga_batch_*).
+# --------------------------------------------------------------------------
+FFS_SCHEDULE_CHROMOSOME = 0
+FFS_SCHEDULE_ISLAND = 1
+FFS_BATCH_MAX_SLOTS = 4096
+
+
+class FfsBatchParams(ctypes.Structure):
+    _fields_ = [
+        ("n_slots", ctypes.c_int32), ("max_jobs", ctypes.c_int32), ("max_genes", ctypes.c_int32),
+        ("max_stages", ctypes.c_int32), ("o_max", ctypes.c_int32), ("max_horizon", ctypes.c_int32),
+        ("ga", FfsGaParams), ("schedule", ctypes.c_int32), ("blocks", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+    ]
+
+
+class FfsBatch(ctypes.Structure):
+    _fields_ = [
+        ("params", FfsBatchParams),
+        ("pop", ctypes.c_int32), ("lds_slots", ctypes.c_int32), ("blocks", ctypes.c_int32),
+        ("omp", ctypes.c_int32),
+        ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
+        ("graph", _vp), ("graph_exec", _vp), ("graph_stream", _vp),
+        ("active", ctypes.c_int32 * FFS_BATCH_MAX_SLOTS),
+        ("generation", ctypes.c_int32 * FFS_BATCH_MAX_SLOTS),
+        ("n_genes", ctypes.c_int32 * FFS_BATCH_MAX_SLOTS),
+    ]
+
+
+_lib.ffs_batch_workspace_size.argtypes = [_P(FfsBatchParams)]
+_lib.ffs_batch_workspace_size.restype = ctypes.c_size_t
+_lib.ga_batch_create.argtypes = [_P(FfsBatch), _P(FfsBatchParams), _vp, ctypes.c_size_t, _vp]
+_lib.ga_batch_set.argtypes = [_P(FfsBatch), ctypes.c_int32, _P(FfsInstance), ctypes.c_uint64,
+                              ctypes.c_uint64, ctypes.c_int32, _vp]
+_lib.ga_batch_clear.argtypes = [_P(FfsBatch), ctypes.c_int32, _vp]
+_lib.ga_batch_step.argtypes = [_P(FfsBatch), ctypes.c_int32, _vp]
+_lib.ga_batch_best.argtypes = [_P(FfsBatch), ctypes.c_int32, _vp, _vp, _vp]
+_lib.ga_batch_view.argtypes = [_P(FfsBatch), ctypes.c_int32, _P(FfsGaView)]
+_lib.ga_batch_destroy.argtypes = [_P(FfsBatch)]
+for _f in ("ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step", "ga_batch_best",
+           "ga_batch_view", "ga_batch_destroy"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+@dataclass
+class BatchConfig:
+    """Room and shape of a batch: every slot holds one instance of at most these sizes."""
+    n_slots: int
+    max_jobs: int
+    max_genes: int
+    max_stages: int
+    o_max: int
+    max_horizon: int
+    ga: GaConfig
+    schedule: int = FFS_SCHEDULE_CHROMOSOME
+    blocks: int = 0
+    use_graph: bool = False
+
+    def c(self):
+        return FfsBatchParams(self.n_slots, self.max_jobs, self.max_genes, self.max_stages,
+                              self.o_max, self.max_horizon, self.ga.c(), self.schedule,
+                              self.blocks, 1 if self.use_graph else 0)
+
+    def workspace_bytes(self) -> int:
+        """Device bytes a batch of this shape needs (ffs_batch_workspace_size)."""
+        need = _lib.ffs_batch_workspace_size(ctypes.byref(self.c()))
+        if need == 0:
+            raise FfsError(FFS_E_INVAL, "ffs_batch_workspace_size")
+        return int(need)
+
+
+class Batch:
+    """Slots of independent instances advanced together on one stream of their own."""
+
+    def __init__(self, cfg: BatchConfig, device="cuda", workspace=None):
+        self.cfg = cfg
+        self.p = cfg.c()
+        self.b = FfsBatch()
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.insts = {}
+        need = _lib.ffs_batch_workspace_size(ctypes.byref(self.p))
+        if need == 0:
+            raise FfsError(FFS_E_INVAL, "ffs_batch_workspace_size")
+        self.ws = workspace if workspace is not None and workspace.numel() >= need else torch.empty(
+            need, dtype=torch.uint8, device=self.device)
+        self._enter()
+        _check(_lib.ga_batch_create(ctypes.byref(self.b), ctypes.byref(self.p), _dptr(self.ws),
+                                    self.ws.numel(), _stream(self.stream)), "ga_batch_create")
+
+    def _enter(self):
+        # work queued on the caller's stream (uploads, tensors) happens first
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    @property
+    def pop(self):
+        return int(self.b.pop)
+
+    def set(self, slot, dinst: DeviceInstance, seed, shop, event):
+        self._enter()
+        _check(_lib.ga_batch_set(ctypes.byref(self.b), int(slot), ctypes.byref(dinst.s), int(seed),
+                                 int(shop), int(event), _stream(self.stream)), "ga_batch_set")
+        self.insts[slot] = dinst
+        self._leave()
+
+    def clear(self, slot):
+        self._enter()
+        _check(_lib.ga_batch_clear(ctypes.byref(self.b), int(slot), _stream(self.stream)),
+               "ga_batch_clear")
+        self.insts.pop(slot, None)
+        self._leave()
+
+    def step(self, n_generations=1):
+        self._enter()
+        _check(_lib.ga_batch_step(ctypes.byref(self.b), int(n_generations), _stream(self.stream)),
+               "ga_batch_step")
+        self._leave()
+
+    def generation(self, slot):
+        return int(self.b.generation[slot])
+
+    def best(self, slot):
+        n = max(int(self.b.n_genes[slot]), 1)
+        prio = torch.empty(n, dtype=torch.int32, device=self.device)
+        obj = torch.empty(1, dtype=torch.int64, device=self.device)
+        self._enter()
+        _check(_lib.ga_batch_best(ctypes.byref(self.b), int(slot), _dptr(prio), _dptr(obj),
+                                  _stream(self.stream)), "ga_batch_best")
+        self._leave()
+        return prio[: self.b.n_genes[slot]], obj
+
+    def _slice(self, ptr, count, dtype):
+        off = ptr - self.ws.data_ptr()
+        size = torch.tensor([], dtype=dtype).element_size()
+        return self.ws[off: off + count * size].view(dtype)
+
+    def view(self, slot):
+        v = FfsGaView()
+        _check(_lib.ga_batch_view(ctypes.byref(self.b), int(slot), ctypes.byref(v)), "ga_batch_view")
+        pop, n, isl = self.pop, int(self.b.n_genes[slot]), self.cfg.ga.islands
+        self._leave()
+        return {
+            "prio": self._slice(v.prio, pop * n, torch.int32).view(pop, n),
+            "obj": self._slice(v.obj, pop, torch.int64),
+            "elite": self._slice(v.elite, isl * n, torch.int32).view(isl, n),
+            "elite_obj": self._slice(v.elite_obj, isl, torch.int64),
+            "work": self._slice(v.work, 1, torch.int64),
+        }
+
+    def status(self):
+        self.stream.synchronize()
+        _check(_lib.ffs_status(_dptr(self.ws), _stream(self.stream)), "ga_batch (device status)")
+
+    def destroy(self):
+        _check(_lib.ga_batch_destroy(ctypes.byref(self.b)), "ga_batch_destroy")
+
+    def __del__(self):
+        try:
+            _lib.ga_batch_destroy(ctypes.byref(self.b))
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# Learned offspring pre-screen (include/ffs_surrogate.h).
+# --------------------------------------------------------------------------
+SG_HIDDEN = 256
+SG_PARAMS = 4 * 256 + 256 + 256 * 256 + 256 + 256 + 1
+SG_MAX_GENES = 256
+SG_MAX_BATCH = 8192
+SG_MAX_VARIANTS = 8
+
+
+class FfsSurrogate(ctypes.Structure):
+    _fields_ = [("theta", _vp), ("adam_m", _vp), ("adam_v", _vp), ("w2_bf16", _vp),
+                ("w2t_bf16", _vp), ("step", ctypes.c_int32)]
+
+
+_lib.sg_refresh.argtypes = [_P(FfsSurrogate), _vp]
+_lib.sg_features.argtypes = [_P(FfsInstance), _vp, _vp, ctypes.c_size_t, _vp]
+_lib.sg_table_workspace_size.argtypes = [ctypes.c_int32]
+_lib.sg_table_workspace_size.restype = ctypes.c_size_t
+_lib.sg_score_table.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t,
+                                _vp]
+_lib.sg_score.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+_lib.sg_train_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.sg_train_workspace_size.restype = ctypes.c_size_t
+_lib.sg_train_step.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                               ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.ga_step_screened.argtypes = [_P(FfsGa), _P(FfsInstance), _P(FfsSurrogate), _vp,
+                                  ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
+for _f in ("sg_refresh", "sg_features", "sg_score_table", "sg_score", "sg_train_step",
+           "ga_step_screened"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class Surrogate:
+    """The surrogate's parameters, Adam moments and bf16 copies of W2 on the device."""
+
+    def __init__(self, theta, device="cuda"):
+        t = torch.as_tensor(np.ascontiguousarray(theta, dtype=np.float32)).to(device)
+        if t.numel() != SG_PARAMS:
+            raise FfsError(FFS_E_INVAL, f"surrogate needs {SG_PARAMS} parameters, got {t.numel()}")
+        self.theta = t.contiguous()
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.w2b = torch.empty(SG_HIDDEN * SG_HIDDEN, dtype=torch.int16, device=device)
+        self.w2tb = torch.empty_like(self.w2b)
+        self.s = FfsSurrogate(self.theta.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                              self.w2b.data_ptr(), self.w2tb.data_ptr(), 0)
+        _check(_lib.sg_refresh(ctypes.byref(self.s), _stream()), "sg_refresh")
+        self._train_ws = None
+        self._table_ws = None
+
+    @property
+    def step(self):
+        return int(self.s.step)
+
+    def features(self, dinst: DeviceInstance) -> torch.Tensor:
+        dev = self.theta.device
+        feats = torch.empty((max(dinst.n_active, 1), 4), dtype=torch.float32, device=dev)
+        ws = torch.empty(FFS_PREPARE_WORKSPACE, dtype=torch.uint8, device=dev)
+        _check(_lib.sg_features(ctypes.byref(dinst.s), _dptr(feats), _dptr(ws), ws.numel(),
+                                _stream()), "sg_features")
+        return feats
+
+    def score_table(self, feats: torch.Tensor, n: int) -> torch.Tensor:
+        need = _lib.sg_table_workspace_size(int(n))
+        if need == 0:
+            raise FfsError(FFS_E_INVAL, "sg_table_workspace_size")
+        if self._table_ws is None or self._table_ws.numel() < need:
+            self._table_ws = torch.empty(need, dtype=torch.uint8, device=self.theta.device)
+        table = torch.empty((n, n), dtype=torch.float32, device=self.theta.device)
+        _check(_lib.sg_score_table(ctypes.byref(self.s), _dptr(feats), int(n), _dptr(table),
+                                   _dptr(self._table_ws), self._table_ws.numel(), _stream()),
+               "sg_score_table")
+        return table
+
+    def score(self, table: torch.Tensor, prio: torch.Tensor) -> torch.Tensor:
+        prio = prio.to(device=self.theta.device, dtype=torch.int32).contiguous()
+        n = int(prio.shape[-1])
+        count = int(prio.numel() // max(n, 1))
+        y = torch.empty(count, dtype=torch.float32, device=self.theta.device)
+        _check(_lib.sg_score(ctypes.byref(self.s), _dptr(table), n, _dptr(prio), count, _dptr(y),
+                             _stream()), "sg_score")
+        return y
+
+    def train_step(self, feats, prio, obj, lr, want_grad=False):
+        """One Adam step; returns (loss tensor [1], gradient [SG_PARAMS] or None)."""
+        dev = self.theta.device
+        prio = prio.to(device=dev, dtype=torch.int32).contiguous()
+        obj = obj.to(device=dev, dtype=torch.int64).contiguous()
+        B, n = int(prio.shape[0]), int(prio.shape[1])
+        need = _lib.sg_train_workspace_size(n, B)
+        if need == 0:
+            raise FfsError(FFS_E_INVAL, "sg_train_workspace_size")
+        if self._train_ws is None or self._train_ws.numel() < need:
+            self._train_ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        grad = torch.empty(SG_PARAMS, dtype=torch.float32, device=dev) if want_grad else None
+        _check(_lib.sg_train_step(ctypes.byref(self.s), _dptr(feats), n, _dptr(prio), _dptr(obj), B,
+                                  float(lr), _dptr(loss), _dptr(grad), _dptr(self._train_ws),
+                                  self._train_ws.numel(), _stream()), "sg_train_step")
+        return loss, grad
