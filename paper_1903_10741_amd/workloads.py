@@ -281,4 +281,78 @@ def random_population(seed: int, pop: int, n: int) -> np.ndarray:
     return np.ascontiguousarray(rng.permuted(base, axis=1), dtype=np.int32)
 
 
+def shop_instance(rng, n_jobs, n_stages, machines, wt=10, percent=55):
+    """One shop drawn like the paper-shaped recipe: P = max(1, round(U{5..50} x U[0.8,1.5])),
+    Q_sm ~ U{2..15}, peak `percent`, R = 0, D = round(U[1.2,2.0] x P-bar)."""
+    nm = np.asarray(machines, np.int32)
+    om = int(nm.max())
+    speed = rng.uniform(0.8, 1.5, size=(n_stages, om))
+    proc = _unrelated(rng, n_jobs, speed)
+    qsm = rng.integers(2, 16, size=(n_stages, om))
+    q_max = peak_limit(qsm, nm, percent)
+    slack = rng.uniform(1.2, 2.0, size=n_jobs)
+    due = round_half_up(slack * mean_proc(proc, nm))
+    return initial_instance(proc, _broadcast_power(qsm, n_jobs), np.zeros(n_jobs), due, nm,
+                            q_max, wt)
+
+
+def shops(seed: int = 0, n_shops: int = 512, jobs=(20, 200), stages=(3, 10), machines=(2, 6),
+          o_max: int = 6):
+    """Independent shops of uneven size: jobs ~ U{20..200}, stages ~ U{3..10}, machines per
+    stage ~ U{2..6}, otherwise the paper-shaped distributions. Every instance is padded to
+    o_max machine columns so that shops can share a batch."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_shops):
+        n = int(rng.integers(jobs[0], jobs[1] + 1))
+        g = int(rng.integers(stages[0], stages[1] + 1))
+        nm = rng.integers(machines[0], machines[1] + 1, size=g)
+        inst = shop_instance(rng, n, g, nm)
+        pad = o_max - inst.o_max
+        if pad > 0:
+            inst.proc = np.pad(inst.proc, ((0, 0), (0, 0), (0, pad)), constant_values=1)
+            inst.power = np.pad(inst.power, ((0, 0), (0, 0), (0, pad)), constant_values=1)
+            inst.machine_free = np.pad(inst.machine_free, ((0, 0), (0, pad)))
+            inst.o_max = o_max
+        out.append(inst)
+    return out
+
+
+def shop_arrivals(seed: int, index: int, inst: Instance, n_events: int) -> List[Arrival]:
+    """Arrival events of one shop: Poisson times over the shop's LB0 like the
+    paper-shaped recipe, U{max(2, n/10)..max(3, n/5)} new jobs each with fresh
+    unrelated-machine times, the shop's machine powers and due slack U[1.2, 2.0]."""
+    rng = np.random.default_rng([seed, index])
+    g, om, nm = int(inst.n_stages), int(inst.o_max), inst.n_machines
+    qsm = np.asarray(inst.power[0]) if inst.n_jobs else np.ones((g, om), np.int32)
+    times = _poisson_times(rng, n_events, makespan_lower_bound(inst.proc, qsm, nm, inst.q_max))
+    lo, hi = max(2, inst.n_jobs // 10), max(3, inst.n_jobs // 5)
+    out = []
+    for t in times:
+        k = int(rng.integers(lo, hi + 1))
+        speed = rng.uniform(0.8, 1.5, size=(g, om))
+        p_new = _unrelated(rng, k, speed)
+        sl = rng.uniform(1.2, 2.0, size=k)
+        out.append(Arrival(t, p_new, _broadcast_power(qsm, k), np.full(k, t, np.int32),
+                           (t + round_half_up(sl * mean_proc(p_new, nm))).astype(np.int32)))
+    return out
+
+
+SERVING_GA = GaParams(8, 8, 16, mig_k=2)   # 1024 individuals per request
+
+SURROGATE_HIDDEN = 256
+
+
+def surrogate_init(seed: int, hidden: int = SURROGATE_HIDDEN) -> np.ndarray:
+    """Initial surrogate parameters, float32, flat layout [W1 (4 x H), b1 (H),
+    W2 (H x H), b2 (H), w3 (H), b3]: weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)),
+    biases 0 except b3 = 12 (near ln of the paper-shaped objectives)."""
+    rng = np.random.default_rng([seed, 0x5047])
+    h = hidden
+    parts = [rng.uniform(-0.5, 0.5, size=4 * h), np.zeros(h),
+             rng.uniform(-1, 1, size=h * h) / np.sqrt(h), np.zeros(h),
+             rng.uniform(-1, 1, size=h) / np.sqrt(h), np.array([12.0])]
+    return np.concatenate(parts).astype(np.float32)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3}
