@@ -16,16 +16,18 @@
  *   c_k  = ((b1 + f0 W1[1]) + f1 W1[2]) + f2 W1[3]            (float32, no FMA)
  *   h1_k = bf16(max(c_k + rank_k W1[0], 0))
  *   h2_k = max(h1_k . bf16(W2) + b2, 0)                       (bf16 MFMA, fp32 accumulate)
- *   y    = b3 + mean over k of h2_k . w3                      (predicts ln obj)
+ *   y    = b3 + mean over k of h2_k . w3     (predicts standardised ln obj, below)
  * The rank is the only input that varies between chromosomes of one
  * instance and takes n values, so layers 1 and 2 are evaluated once per
  * (job, rank) pair, an n^2 x 256 by 256 x 256 matrix-core product, and a
  * chromosome's score is a gather of n table entries.
  *
  * Parameters are float32, flat: [W1 (4 x H), b1 (H), W2 (H x H, row = input
- * unit), b2 (H), w3 (H), b3 (1)]; FFS_SG_PARAMS floats. Training minimises
- * mean (y - ln obj)^2 over a batch with Adam (beta1 0.9, beta2 0.999,
- * eps 1e-8, bias-corrected).
+ * unit), b2 (H), w3 (H), b3 (1)]; FFS_SG_PARAMS floats. The network predicts
+ * ln(obj) standardised within the chromosome's population (screening only
+ * compares the candidates of one cell, so a population's offset and spread
+ * carry nothing it needs); training minimises mean (y - t)^2 over a batch
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
  *
  * Conventions as in ffsga.h: device pointers are caller-owned GPU memory,
  * calls are asynchronous on `stream` (a hipStream_t, NULL = default), never
@@ -84,23 +86,33 @@ int sg_score_table(const ffs_surrogate *model, const float *feats, int32_t n_gen
 int sg_score(const ffs_surrogate *model, const float *table, int32_t n_genes, const int32_t *prio,
              int32_t count, float *y, void *stream);
 
+/* Training targets: t[i] = (ln obj[i] - mean) / sd over each group of `group`
+ * consecutive entries (one population; the last group may be shorter), mean
+ * and population standard deviation in float64 summed in index order, the
+ * result rounded to float32; a group with sd = 0 gets 0. obj device int64
+ * [count] (> 0), target device float32 [count]. workspace: device, at least
+ * FFS_PREPARE_WORKSPACE bytes; an objective <= 0 is reported by the next
+ * ffs_status(workspace) as FFS_E_INVAL. */
+int sg_targets(const int64_t *obj, int32_t count, int32_t group, float *target, void *workspace,
+               size_t workspace_bytes, void *stream);
+
 /* Device workspace bytes of sg_train_step for n_genes and batch. */
 size_t sg_train_workspace_size(int32_t n_genes, int32_t batch);
 
 /* One Adam step on a batch of decoder-labelled chromosomes: prio device
- * [batch][n_genes], obj device int64 [batch] (> 0, the exact eq. (1)
- * objectives). The step minimises mean (y - ln obj)^2 with learning rate
- * lr, increments model->step and refreshes the bf16 copies of W2.
+ * [batch][n_genes], target device float32 [batch] (from sg_targets on the
+ * exact eq. (1) objectives). The step minimises mean (y - t)^2 with learning
+ * rate lr, increments model->step and refreshes the bf16 copies of W2.
  * loss (device float32 [1], may be NULL) receives the batch loss before the
  * step; grad (device float32 [FFS_SG_PARAMS], may be NULL) the gradient.
- * A batch holding a gene outside 1..n or an objective <= 0 is found on the
+ * A batch holding a gene outside 1..n or a target that is not finite is found on the
  * device: the step then leaves the parameters and moments unchanged and the
  * next ffs_status(workspace) returns FFS_E_INVAL (model->step still counts
  * the call). The workspace starts with the 256-byte status block ffs_status
  * reads; its status is cleared at the start of every step.
  * Errors: FFS_E_INVAL, FFS_E_WORKSPACE, FFS_E_DEVICE. */
 int sg_train_step(ffs_surrogate *model, const float *feats, int32_t n_genes, const int32_t *prio,
-                  const int64_t *obj, int32_t batch, float lr, float *loss, float *grad,
+                  const float *target, int32_t batch, float lr, float *loss, float *grad,
                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* n_generations screened GA generations on ga (an ffs_ga of ffsga.h, set up

@@ -19,7 +19,8 @@ every fitness). This module states what the GPU kernels compute, plainly:
   layer 2:   a2 = h1 . bf16(W2) + b2     (bf16 operands, exact products, summed)
              h2 = max(a2, 0)
   pool/out:  z = mean over the chromosome's jobs of h2;  y = z . w3 + b3
-  loss:      L = mean over the batch of (y - ln obj)^2
+  target:    t = ln obj standardised within the chromosome's population
+  loss:      L = mean over the batch of (y - t)^2
 
 The forward keeps float32 exactly where the kernels do (features, layer 1,
 the bf16 roundings) and sums layer 2, the pool and the output in float64;
@@ -272,6 +273,19 @@ def grad_bound(p: dict, f: dict) -> dict:
     dH1abs = (Gabs + e_Gb) @ np.abs(W2).T
     out["b1"] = (m1 * e_dH1).sum(axis=0) + _gamma(Q) * (m1 * dH1abs).sum(axis=0)
     out["W1"] = np.abs(x).T @ (m1 * e_dH1) + (_gamma(Q) + U32) * (np.abs(x).T @ (m1 * dH1abs))
+    return out
+
+
+def targets(obj, group: int) -> np.ndarray:
+    """Training targets, float64: ln obj standardised within each group of `group`
+    consecutive entries (mean and population standard deviation; 0 where the
+    deviation is 0)."""
+    lo = np.log(np.asarray(obj, np.float64))
+    out = np.zeros_like(lo)
+    for g0 in range(0, len(lo), group):
+        x = lo[g0:g0 + group]
+        sd = x.std()
+        out[g0:g0 + group] = (x - x.mean()) / sd if sd > 0 else 0.0
     return out
 
 

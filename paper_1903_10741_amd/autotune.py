@@ -46,14 +46,16 @@ def signature(insts: Sequence, ga) -> str:
 
 
 def default_candidates(n_cu: int, horizon_max: int) -> List[Candidate]:
+    """On-chip profile slots from 4096 up to the largest horizon (at most 32768;
+    a decode whose schedule outgrows them is redone off chip), persistent grids of
+    4, 8 and 16 blocks per CU, both schedules, graph replay; one eager candidate."""
     out = []
-    for lds in (2048, 4096, 8192):
-        if lds > 2 * horizon_max and lds != 2048:
-            continue
+    ladder = [x for x in (4096, 8192, 16384, 32768) if x < 2 * horizon_max] or [4096]
+    for lds in ladder:
         for blocks in (4 * n_cu, 8 * n_cu, 16 * n_cu):
             out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, lds, blocks, True))
         out.append(Candidate(ffsga.FFS_SCHEDULE_ISLAND, lds, 8 * n_cu, True))
-    out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, 4096, 8 * n_cu, False))
+    out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, ladder[-1], 8 * n_cu, False))
     return out
 
 
@@ -89,7 +91,7 @@ def time_candidate(dev_insts, insts, ga, horizon_max, cand: Candidate, generatio
 
 
 def tune(dev_insts, insts, ga, candidates: Optional[List[Candidate]] = None,
-         cache_path: Optional[str] = None, generations=3) -> TuneResult:
+         cache_path: Optional[str] = None, generations=3, log=None) -> TuneResult:
     horizon_max = max(d.horizon for d in dev_insts)
     key = signature(insts, ga)
     cache: Dict[str, dict] = {}
@@ -106,6 +108,8 @@ def tune(dev_insts, insts, ga, candidates: Optional[List[Candidate]] = None,
         us = time_candidate(dev_insts, insts, ga, horizon_max, cand, generations)
         table.append({**asdict(cand), "us_per_generation": us,
                       "tuning_s": time.perf_counter() - t0})
+        if log:
+            log(f"autotune {asdict(cand)}: {us:.0f} us/generation")
     best = min(table, key=lambda r: r["us_per_generation"])
     res = TuneResult(Candidate(best["schedule"], best["lds_slots"], best["blocks"],
                                best["use_graph"]), best["us_per_generation"], table)

@@ -246,16 +246,16 @@ __global__ __launch_bounds__(256) void table_sum_kernel(const float *r_part, int
 }
 
 // ---------------------------------------------------------------------------
-// Training-step input check: every gene in 1..n and every objective > 0, else
+// Training-step input check: every gene in 1..n and every target finite, else
 // bit 0 of the status word; the later kernels of the step then do nothing.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1) void clear_status_kernel(int32_t *status) { status[0] = 0; }
 
-__global__ __launch_bounds__(256) void validate_kernel(const int32_t *prio, const int64_t *obj,
+__global__ __launch_bounds__(256) void validate_kernel(const int32_t *prio, const float *target,
                                                        int n, int B, int32_t *status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  bool bad = obj[b] <= 0;
+  bool bad = !(fabsf(target[b]) <= 3.0e38f);   // NaN or infinite
   for (int k = 0; k < n; ++k) {
     const int v = prio[(size_t)b * n + k];
     bad |= v < 1 || v > n;
@@ -264,12 +264,47 @@ __global__ __launch_bounds__(256) void validate_kernel(const int32_t *prio, cons
 }
 
 // ---------------------------------------------------------------------------
+// Training targets: ln obj standardised within each group of `group`
+// consecutive chromosomes (one population), mean and population standard
+// deviation in float64, summed in index order; a constant group gets 0.
+// One block per group.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void targets_kernel(const int64_t *obj, int count, int group,
+                                                     float *target, int32_t *status) {
+  __shared__ double stat[2];
+  const int g0 = blockIdx.x * group;
+  const int g1 = g0 + group < count ? g0 + group : count;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    bool bad = false;
+    for (int i = g0; i < g1; ++i) {
+      bad |= obj[i] <= 0;
+      s += log((double)(obj[i] > 0 ? obj[i] : 1));
+    }
+    const double mean = s / (double)(g1 - g0);
+    double v = 0.0;
+    for (int i = g0; i < g1; ++i) {
+      const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - mean;
+      v += d * d;
+    }
+    stat[0] = mean;
+    stat[1] = sqrt(v / (double)(g1 - g0));
+    if (bad) atomicOr(status, 1);
+  }
+  __syncthreads();
+  for (int i = g0 + threadIdx.x; i < g1; i += blockDim.x) {
+    const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - stat[0];
+    target[i] = stat[1] > 0.0 ? (float)(d / stat[1]) : 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Batch forward (pool order): z_b = (sum over k of h2[k][prio_bk]) / n,
-// y_b = b3 + z_b . w3, target ln obj_b, dy_b = 2 (y_b - t_b) / B.
+// y_b = b3 + z_b . w3, dy_b = 2 (y_b - t_b) / B.
 // One wave per chromosome, 4 units per lane.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void batch_fwd_kernel(const float *theta, const float *h2,
-                                                       const int32_t *prio, const int64_t *obj,
+                                                       const int32_t *prio, const float *target,
                                                        int n, int B, float *z, float *dy,
                                                        float *sq, const int32_t *status) {
   if (status[0]) return;
@@ -292,7 +327,7 @@ __global__ __launch_bounds__(64) void batch_fwd_kernel(const float *theta, const
   part = __shfl(part, 0);
   if (lane == 0) {
     const float y = __fadd_rn(theta[kB3], part);
-    const float t = (float)log((double)obj[b]);
+    const float t = target[b];
     const float d = __fsub_rn(y, t);
     dy[b] = __fdiv_rn(__fmul_rn(2.f, d), (float)B);
     sq[b] = __fmul_rn(d, d);
@@ -586,11 +621,24 @@ size_t sg_train_workspace_size(int32_t n_genes, int32_t batch) {
   return train_ws(nullptr, n_genes, batch).total;
 }
 
+int sg_targets(const int64_t *obj, int32_t count, int32_t group, float *target, void *workspace,
+               size_t workspace_bytes, void *stream) {
+  if (!obj || !target || count < 0 || group < 1) return FFS_E_INVAL;
+  if (!workspace || workspace_bytes < (size_t)kHeaderBytes) return FFS_E_WORKSPACE;
+  if (count == 0) return FFS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t *status = (int32_t *)workspace;
+  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, status);
+  hipLaunchKernelGGL(targets_kernel, dim3((count + group - 1) / group), dim3(256), 0, s, obj,
+                     count, group, target, status);
+  return ok(hipGetLastError()) ? FFS_OK : FFS_E_DEVICE;
+}
+
 int sg_train_step(ffs_surrogate *m, const float *feats, int32_t n, const int32_t *prio,
-                  const int64_t *obj, int32_t B, float lr, float *loss, float *grad,
+                  const float *target, int32_t B, float lr, float *loss, float *grad,
                   void *workspace, size_t workspace_bytes, void *stream) {
   if (!m || !m->theta || !m->adam_m || !m->adam_v || !m->w2_bf16 || !m->w2t_bf16 || !feats ||
-      !prio || !obj || n < 1 || n > FFS_SG_MAX_GENES || B < 1 || B > FFS_SG_MAX_BATCH ||
+      !prio || !target || n < 1 || n > FFS_SG_MAX_GENES || B < 1 || B > FFS_SG_MAX_BATCH ||
       !(lr > 0.f) || m->step < 0)
     return FFS_E_INVAL;
   const TrainWs L = train_ws(workspace, n, B);
@@ -600,13 +648,14 @@ int sg_train_step(ffs_surrogate *m, const float *feats, int32_t n, const int32_t
   const float *th = m->theta;
   const int32_t *st = L.status;
   hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, L.status);
-  hipLaunchKernelGGL(validate_kernel, dim3(grid1(B)), dim3(256), 0, s, prio, obj, n, B, L.status);
+  hipLaunchKernelGGL(validate_kernel, dim3(grid1(B)), dim3(256), 0, s, prio, target, n, B,
+                     L.status);
   hipLaunchKernelGGL(ctab_kernel, dim3(grid1(n * H)), dim3(256), 0, s, th, feats, n, L.ctab);
   hipLaunchKernelGGL(table_fwd_kernel<true>, dim3(blocks, H / BN), dim3(256), 0, s, th,
                      (const float *)L.ctab, (const uint16_t *)m->w2t_bf16, n, L.h2,
                      (float *)nullptr);
-  hipLaunchKernelGGL(batch_fwd_kernel, dim3(B), dim3(64), 0, s, th, (const float *)L.h2, prio, obj,
-                     n, B, L.z, L.dy, L.sq, st);
+  hipLaunchKernelGGL(batch_fwd_kernel, dim3(B), dim3(64), 0, s, th, (const float *)L.h2, prio,
+                     target, n, B, L.z, L.dy, L.sq, st);
   hipLaunchKernelGGL(dtable_kernel, dim3(n), dim3(256), (size_t)B * 8, s, prio,
                      (const float *)L.dy, n, B, L.D, st);
   hipLaunchKernelGGL(head_kernel, dim3(1), dim3(256), 0, s, (const float *)L.dy,

@@ -376,7 +376,7 @@ def exported_symbols():
                  "ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step",
                  "ga_batch_best", "ga_batch_view", "ga_batch_destroy", "sg_refresh",
                  "sg_features", "sg_table_workspace_size", "sg_score_table", "sg_score",
-                 "sg_train_workspace_size", "sg_train_step", "ga_step_screened"):
+                 "sg_train_workspace_size", "sg_train_step", "ga_step_screened", "sg_targets"):
         if hasattr(_lib, name):
             names.append(name)
     return names
@@ -571,6 +571,7 @@ _lib.sg_table_workspace_size.restype = ctypes.c_size_t
 _lib.sg_score_table.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t,
                                 _vp]
 _lib.sg_score.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+_lib.sg_targets.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]
 _lib.sg_train_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
 _lib.sg_train_workspace_size.restype = ctypes.c_size_t
 _lib.sg_train_step.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32,
@@ -578,7 +579,7 @@ _lib.sg_train_step.argtypes = [_P(FfsSurrogate), _vp, ctypes.c_int32, _vp, _vp, 
 _lib.ga_step_screened.argtypes = [_P(FfsGa), _P(FfsInstance), _P(FfsSurrogate), _vp,
                                   ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]
 for _f in ("sg_refresh", "sg_features", "sg_score_table", "sg_score", "sg_train_step",
-           "ga_step_screened"):
+           "ga_step_screened", "sg_targets"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -633,11 +634,22 @@ class Surrogate:
                              _stream()), "sg_score")
         return y
 
-    def train_step(self, feats, prio, obj, lr, want_grad=False):
+    def targets(self, obj, group):
+        """Training targets: ln obj standardised within groups of `group` (sg_targets)."""
+        dev = self.theta.device
+        obj = obj.to(device=dev, dtype=torch.int64).contiguous()
+        t = torch.empty(obj.numel(), dtype=torch.float32, device=dev)
+        ws = torch.empty(FFS_PREPARE_WORKSPACE, dtype=torch.uint8, device=dev)
+        _check(_lib.sg_targets(_dptr(obj), obj.numel(), int(group), _dptr(t), _dptr(ws), ws.numel(),
+                               _stream()), "sg_targets")
+        _check(_lib.ffs_status(_dptr(ws), _stream()), "sg_targets (device status)")
+        return t
+
+    def train_step(self, feats, prio, target, lr, want_grad=False):
         """One Adam step; returns (loss tensor [1], gradient [SG_PARAMS] or None)."""
         dev = self.theta.device
         prio = prio.to(device=dev, dtype=torch.int32).contiguous()
-        obj = obj.to(device=dev, dtype=torch.int64).contiguous()
+        target = target.to(device=dev, dtype=torch.float32).contiguous()
         B, n = int(prio.shape[0]), int(prio.shape[1])
         need = _lib.sg_train_workspace_size(n, B)
         if need == 0:
@@ -646,7 +658,7 @@ class Surrogate:
             self._train_ws = torch.empty(need, dtype=torch.uint8, device=dev)
         loss = torch.empty(1, dtype=torch.float32, device=dev)
         grad = torch.empty(SG_PARAMS, dtype=torch.float32, device=dev) if want_grad else None
-        _check(_lib.sg_train_step(ctypes.byref(self.s), _dptr(feats), n, _dptr(prio), _dptr(obj), B,
+        _check(_lib.sg_train_step(ctypes.byref(self.s), _dptr(feats), n, _dptr(prio), _dptr(target), B,
                                   float(lr), _dptr(loss), _dptr(grad), _dptr(self._train_ws),
                                   self._train_ws.numel(), _stream()), "sg_train_step")
         return loss, grad

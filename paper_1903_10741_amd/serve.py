@@ -259,11 +259,20 @@ class Server:
                 self.adm.release(r, "done")
 
     def run(self, schedule: Sequence[Tuple[float, int]], time_limit_s: Optional[float] = None,
-            idle_sleep_s: float = 1e-4) -> dict:
-        """Serve a request stream of (offset in seconds, shop). Returns the metrics."""
+            idle_sleep_s: float = 1e-4, log: Optional[Callable[[str], None]] = None,
+            log_every: int = 100) -> dict:
+        """Serve a request stream of (offset in seconds, shop). Returns the metrics.
+        `log`, if given, receives a progress line every `log_every` finished requests."""
         t0 = self.clock()
         pending = deque(sorted(schedule))
+        reported = 0
         while pending or self.adm.queue or self.running:
+            if log:
+                n_done = sum(r.status in ("done", "late") for r in self.requests)
+                if n_done >= reported + log_every:
+                    reported = n_done
+                    log(f"{n_done} requests served, {len(self.adm.queue)} queued, "
+                        f"{len(self.running)} running, {self.clock() - t0:.1f} s")
             now = self.clock() - t0
             while pending and pending[0][0] <= now:
                 t, shop = pending.popleft()

@@ -346,12 +346,12 @@ SURROGATE_HIDDEN = 256
 def surrogate_init(seed: int, hidden: int = SURROGATE_HIDDEN) -> np.ndarray:
     """Initial surrogate parameters, float32, flat layout [W1 (4 x H), b1 (H),
     W2 (H x H), b2 (H), w3 (H), b3]: weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)),
-    biases 0 except b3 = 12 (near ln of the paper-shaped objectives)."""
+    biases 0 (the targets are standardised)."""
     rng = np.random.default_rng([seed, 0x5047])
     h = hidden
     parts = [rng.uniform(-0.5, 0.5, size=4 * h), np.zeros(h),
              rng.uniform(-1, 1, size=h * h) / np.sqrt(h), np.zeros(h),
-             rng.uniform(-1, 1, size=h) / np.sqrt(h), np.array([12.0])]
+             rng.uniform(-1, 1, size=h) / np.sqrt(h), np.array([0.0])]
     return np.concatenate(parts).astype(np.float32)
 
 

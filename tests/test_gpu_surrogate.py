@@ -109,10 +109,24 @@ def test_scores_repeat_and_match_between_entry_points():
 
 
 def _batch(inst, B, seed):
-    """Chromosomes and their exact objectives from the oracle's decoder."""
+    """Chromosomes, their exact objectives from the oracle's decoder, and the
+    oracle's training targets for them (one group), rounded to float32."""
     prio = W.random_population(seed, B, inst.n_active)
-    obj = oracle.decode_pop(inst, prio, n_threads=8)
-    return prio, np.asarray(obj, np.int64)
+    obj = np.asarray(oracle.decode_pop(inst, prio, n_threads=8), np.int64)
+    return prio, obj, S.targets(obj, B).astype(np.float32)
+
+
+def test_targets_match_oracle():
+    torch, ffsga = _ffs()
+    m = ffsga.Surrogate(W.surrogate_init(0))
+    inst = _instances()[2]
+    prio, obj, _ = _batch(inst, 1000, 3)
+    obj = np.concatenate([obj, np.full(7, 1234, np.int64)])      # a constant last group
+    for group in (1000, 333, 7):
+        _say("targets group", group)
+        got = m.targets(torch.from_numpy(obj), group).cpu().numpy().astype(np.float64)
+        want = S.targets(obj, group)
+        assert (np.abs(got - want) <= S.U32 * np.abs(want) + 1e-9).all()
 
 
 @pytest.mark.parametrize("which,B", [(1, 33), (2, 256), (3, 97)])
@@ -125,10 +139,10 @@ def test_gradient_within_bound(which, B):
     m = ffsga.Surrogate(th)
     d = ffsga.DeviceInstance.from_host(inst)
     feats = m.features(d)
-    prio, obj = _batch(inst, B, 20 + which)
-    loss, grad = m.train_step(feats, torch.from_numpy(prio), torch.from_numpy(obj), 1e-3,
+    prio, obj, tgt = _batch(inst, B, 20 + which)
+    loss, grad = m.train_step(feats, torch.from_numpy(prio), torch.from_numpy(tgt), 1e-3,
                               want_grad=True)
-    L, g, f = S.loss_and_grad(p, S.job_features(inst), prio, np.log(obj.astype(np.float64)))
+    L, g, f = S.loss_and_grad(p, S.job_features(inst), prio, tgt.astype(np.float64))
     bnd = S.grad_bound(p, f)
     got = S.unflatten(grad.cpu().numpy())
     for k in g:
@@ -157,13 +171,13 @@ def test_train_step_repeats_bit_for_bit():
     torch, ffsga = _ffs()
     inst = _instances()[2]
     th, _ = _params(5)
-    prio, obj = _batch(inst, 200, 9)
+    prio, obj, tgt = _batch(inst, 200, 9)
     out = []
     for _ in range(2):
         m = ffsga.Surrogate(th)
         feats = m.features(ffsga.DeviceInstance.from_host(inst))
         for _ in range(3):
-            loss, grad = m.train_step(feats, torch.from_numpy(prio), torch.from_numpy(obj), 3e-3,
+            loss, grad = m.train_step(feats, torch.from_numpy(prio), torch.from_numpy(tgt), 3e-3,
                                       want_grad=True)
         out.append((m.theta.clone(), grad.clone(), loss.clone()))
     for a, b in zip(out[0], out[1]):
@@ -179,13 +193,16 @@ def test_training_lowers_the_loss():
     feats = m.features(d)
     prio = torch.from_numpy(W.random_population(3, 4096, inst.n_active)).cuda()
     obj = ffsga.ffs_decode(d, prio)
+    tgt = m.targets(obj, 4096)
     losses = []
     for step in range(150):
         sl = slice((step % 4) * 1024, (step % 4 + 1) * 1024)
-        loss, _ = m.train_step(feats, prio[sl], obj[sl], 3e-3)
+        loss, _ = m.train_step(feats, prio[sl], tgt[sl], 3e-3)
         losses.append(float(loss.item()))
     assert np.isfinite(losses).all()
-    assert np.mean(losses[-10:]) < 0.2 * losses[0]
+    # standardised targets: predicting 0 scores about 1; an additive model of the
+    # (job, rank) pairs explains a good part of the variance of random chromosomes
+    assert np.mean(losses[-10:]) < min(0.85 * losses[0], 0.9)
 
 
 GA = W.GaParams(2, 4, 4, mig_interval=2, mig_k=1)
@@ -300,11 +317,12 @@ def test_trained_surrogate_gains_over_the_plain_generation():
     prio, obj = torch.cat(prios), torch.cat(objs)
     m = ffsga.Surrogate(W.surrogate_init(0))
     feats = m.features(d)
+    tgt = m.targets(obj, ga.pop)
     gen = torch.Generator().manual_seed(0)
     for ep in range(3):
         perm = torch.randperm(prio.shape[0], generator=gen).cuda()
         for i in range(0, prio.shape[0] - 2047, 2048):
-            m.train_step(feats, prio[perm[i:i + 2048]], obj[perm[i:i + 2048]], 1e-3)
+            m.train_step(feats, prio[perm[i:i + 2048]], tgt[perm[i:i + 2048]], 1e-3)
     table = m.score_table(feats, inst.n_active)
     g0 = ffsga.GA(d, cfg, 999, 0, 0)
     v = g0.view()

@@ -274,3 +274,17 @@ def test_grad_bound_covers_float32_table_evaluation():
         assert (err <= bnd[k] + 1e-30).all(), (k, float((err - bnd[k]).max()))
         rel = np.linalg.norm(err) / max(np.linalg.norm(g[k]), 1e-30)
         assert rel < 2 ** -6, (k, rel)          # the bound is tight enough to mean something
+
+
+def test_targets_are_per_group_zscores_of_ln_obj():
+    from scipy import stats
+    rng = np.random.default_rng(4)
+    obj = rng.integers(1000, 900000, size=1000)
+    t = S.targets(obj, 250)
+    for g in range(4):
+        seg = slice(250 * g, 250 * (g + 1))
+        assert np.allclose(t[seg], stats.zscore(np.log(obj[seg].astype(np.float64))), atol=1e-12)
+        assert np.array_equal(np.argsort(t[seg], kind="stable"), np.argsort(obj[seg], kind="stable"))
+    assert (S.targets(np.full(5, 77), 5) == 0).all()
+    short = S.targets(obj[:10], 4)                      # last group of 2
+    assert np.allclose(short[8:], [-1.0, 1.0]) or np.allclose(short[8:], [1.0, -1.0])
