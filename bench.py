@@ -92,7 +92,8 @@ def bench_batch(args):
     b.status()
     decodes = len(shops) * ga.pop * (1 + gens)
     # roofline of the generation kernel: a timed eager run of the same shape
-    rcand = autotune.Candidate(tune.best.schedule, tune.best.lds_slots, tune.best.blocks, False)
+    rcand = autotune.Candidate(tune.best.schedule, tune.best.lds_slots, tune.best.blocks, False,
+                               tune.best.profile_classes)
     rb = ffsga.Batch(autotune.batch_config(shops, ga, horizon, rcand))
     for s, d in enumerate(dev):
         rb.set(s, d, args.seed, s, 0)
@@ -137,7 +138,8 @@ def bench_serve(args):
     srv = Server(shops, arrs, W.SERVING_GA, generations=gens, n_slots=args.slots,
                  gens_per_tick=args.gens_per_tick, seed=args.seed,
                  tuning={"use_graph": True, "blocks": tune.best.blocks,
-                         "lds_slots": tune.best.lds_slots, "schedule": tune.best.schedule})
+                         "lds_slots": tune.best.lds_slots, "schedule": tune.best.schedule,
+                         "profile_classes": tune.best.profile_classes})
     progress("serving starts")
     sched = poisson_schedule(args.seed, args.rate, [n_events] * len(shops))
     torch.cuda.synchronize()

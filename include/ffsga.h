@@ -203,6 +203,7 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
 #define FFS_SCHEDULE_CHROMOSOME 0   /* one wave decodes one child */
 #define FFS_SCHEDULE_ISLAND 1       /* one wave breeds, decodes and replaces one island */
 #define FFS_BATCH_MAX_SLOTS 4096
+#define FFS_BATCH_MAX_CLASSES 4
 
 typedef struct {
   int32_t n_slots;         /* instances held at once, <= FFS_BATCH_MAX_SLOTS */
@@ -215,6 +216,14 @@ typedef struct {
   int32_t schedule;        /* FFS_SCHEDULE_CHROMOSOME or FFS_SCHEDULE_ISLAND */
   int32_t blocks;          /* persistent grid size (resident waves), 0 = 8 per CU */
   int32_t use_graph;       /* capture one generation in a hipGraph and replay it */
+  int32_t profile_classes; /* 0 or 1: every decode keeps ga.lds_slots profile slots on chip.
+                              C in 2..FFS_BATCH_MAX_CLASSES: size classes lds_slots / 2^(C-1),
+                              ..., lds_slots (rounded up to multiples of 64); each slot takes the
+                              smallest class holding 5/4 of the longest schedule of its
+                              generation 0 (measured on the device) and each generation launches
+                              once per class with that class's LDS, so short schedules keep more
+                              waves per CU. Results do not depend on it: a decode that outgrows
+                              its class is redone off chip. */
 } ffs_batch_params;
 
 typedef struct {

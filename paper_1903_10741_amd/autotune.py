@@ -27,6 +27,7 @@ class Candidate:
     lds_slots: int
     blocks: int
     use_graph: bool
+    profile_classes: int = 1
 
 
 @dataclass
@@ -55,6 +56,11 @@ def default_candidates(n_cu: int, horizon_max: int) -> List[Candidate]:
         for blocks in (4 * n_cu, 8 * n_cu, 16 * n_cu):
             out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, lds, blocks, True))
         out.append(Candidate(ffsga.FFS_SCHEDULE_ISLAND, lds, 8 * n_cu, True))
+        # size classes from 2048 up to lds (at most 4)
+        cls = min(ffsga.FFS_BATCH_MAX_CLASSES, max(1, (lds // 2048).bit_length()))
+        if cls > 1:
+            for blocks in (8 * n_cu, 16 * n_cu):
+                out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, lds, blocks, True, cls))
     out.append(Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, ladder[-1], 8 * n_cu, False))
     return out
 
@@ -65,7 +71,7 @@ def batch_config(insts, ga, horizon_max, cand: Candidate, n_slots=None) -> ffsga
         max_genes=max(i.n_active for i in insts), max_stages=max(int(i.n_stages) for i in insts),
         o_max=max(int(i.o_max) for i in insts), max_horizon=horizon_max,
         ga=ffsga.GaConfig.of(ga, lds_slots=cand.lds_slots), schedule=cand.schedule,
-        blocks=cand.blocks, use_graph=cand.use_graph)
+        blocks=cand.blocks, use_graph=cand.use_graph, profile_classes=cand.profile_classes)
 
 
 def time_candidate(dev_insts, insts, ga, horizon_max, cand: Candidate, generations=3,
@@ -112,7 +118,8 @@ def tune(dev_insts, insts, ga, candidates: Optional[List[Candidate]] = None,
             log(f"autotune {asdict(cand)}: {us:.0f} us/generation")
     best = min(table, key=lambda r: r["us_per_generation"])
     res = TuneResult(Candidate(best["schedule"], best["lds_slots"], best["blocks"],
-                               best["use_graph"]), best["us_per_generation"], table)
+                               best["use_graph"], best["profile_classes"]),
+                     best["us_per_generation"], table)
     if cache_path:
         cache[key] = {"best": asdict(res.best), "us_per_generation": res.us_per_generation,
                       "table": table}

@@ -132,6 +132,8 @@ struct LdsProfile {
   __device__ void add(int x, uint32_t q) const {
     atomicAdd((uint32_t *)(p + (x & ~3)), q << (8 * (x & 3)));
   }
+  // Add four packed byte increments to the word of slots [x4, x4 + 4), x4 % 4 == 0.
+  __device__ void add_word(int x4, uint32_t w) const { atomicAdd((uint32_t *)(p + x4), w); }
   __device__ void order() const { __asm__ volatile("" ::: "memory"); }
 };
 
@@ -153,6 +155,7 @@ struct GlobalProfile {
   __device__ void add(int x, uint32_t q) const {
     atomicAdd((uint32_t *)(p + (x & ~3)), q << (8 * (x & 3)));
   }
+  __device__ void add_word(int x4, uint32_t w) const { atomicAdd((uint32_t *)(p + x4), w); }
   __device__ void order() const { __threadfence(); }
 };
 
@@ -230,7 +233,8 @@ __device__ __forceinline__ int wave_max32(int v) {
 // moves the start past the last of them inside the window.
 template <int MAXM, bool PLAN, class Prof>
 __device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64_t *obj_out,
-                           int64_t *work_out, int32_t *start_out, int32_t *mach_out) {
+                           int64_t *work_out, int32_t *start_out, int32_t *mach_out,
+                           int32_t *span_max = nullptr) {
   const int lane = __lane_id();
   const int n = I.n;
   const u64 below = (1ull << lane) - 1;
@@ -337,23 +341,32 @@ __device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64
       int t = t0, scan = min(t0, cap);
       uint32_t v = prof.get(scan + lane);
       for (;;) {
-        const int slot = scan + lane;
-        const u64 hit = ballot64(slot >= t && slot < t + p && v > thr);
-        if (!hit && (t + p <= scan + kWave || scan + kWave >= cap)) break;
+        // slots of [t, t + p) in this chunk (one unsigned compare) that break the peak
+        const u64 hit = ballot64((uint32_t)(scan + lane - t) < (uint32_t)p) & ballot64(v > thr);
         if (hit) {
           t = scan + (kWave - __clzll(hit));
-        } else {
-          scan += kWave;
-          v = prof.get(scan + lane);
+          continue;
         }
+        if (t + p <= scan + kWave || scan + kWave >= cap) break;
+        scan += kWave;
+        v = prof.get(scan + lane);
       }
-      // Commit: lanes past the window add 0. A window past the on-chip slots
-      // (found once per stage from the machines' end times) makes this decode
-      // be redone off chip; reads stay in the zero padding and writes are
-      // clamped meanwhile.
-      prof.add(min(t + lane, cap - 1), lane < p ? (uint32_t)q : 0u);
-      if (p > kWave)
-        for (int b = lane + kWave; b < p; b += kWave) prof.add(min(t + b, cap - 1), (uint32_t)q);
+      // Commit q on [t, t + p). The lanes cover the word-aligned slots
+      // [base, base + 64): each quad of lanes holds one profile word, sums its
+      // four byte increments (no carries: every byte stays <= Q_max) and its
+      // first lane adds the word, so no two lanes add to one word. A window
+      // past the on-chip slots (found once per stage from the machines' end
+      // times) makes this decode be redone off chip; reads stay in the zero
+      // padding and writes are clamped meanwhile.
+      {
+        const int base = t & ~3;
+        uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
+        c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
+        c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);
+        if ((lane & 3) == 0 && c != 0u) prof.add_word(min(base + lane, cap - 4), c);
+        if (t - base + p > kWave)  // windows longer than the lanes
+          for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
+      }
       prof.order();
       const int end = t + p + rs;
       fr = lane == mb ? end : fr;
@@ -389,7 +402,9 @@ __device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64
     cmax = max(cmax, c);
   }
   tard = wave_sum64(tard);
-  cmax = max(wave_max32(cmax), I.frozen_cmax);
+  cmax = wave_max32(cmax);
+  if (span_max && lane == 0) atomicMax(span_max, cmax - I.rs);  // profile slots this decode used
+  cmax = max(cmax, I.frozen_cmax);
   if (lane == 0) {
     *obj_out = (int64_t)I.wt * (I.frozen_t + tard) + cmax;
     if (work_out) *work_out = work;
@@ -928,6 +943,8 @@ struct BatchSlot {
   int32_t gen;          // generations run since the slot was set (advanced on the device)
   int32_t active;
   int32_t cap;          // on-chip profile slots of this slot's decodes
+  int32_t cls;          // profile size class: the generation launch that decodes this slot
+  int32_t span;         // longest schedule (end - RS) of generation 0
 };
 
 struct BatchArgs {
@@ -981,16 +998,16 @@ __device__ __forceinline__ GaDev slot_ga(const BatchSlot &S, const BatchArgs &B,
 // off-chip profile.
 template <int MAXM>
 __device__ void decode_slot(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
-                            const GlobalProfile &gp) {
+                            const GlobalProfile &gp, int32_t *span_max = nullptr) {
   int64_t work = 0;
   int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
-                                    nullptr);
+                                    nullptr, span_max);
   if (st == kDecOverflow) {
     const int32_t *src = A.prio_out + (size_t)i * I.n;
     for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];
     __asm__ volatile("" ::: "memory");
     work = 0;
-    st = decode_core<MAXM, false>(I, l, gp, A.obj_out + i, &work, nullptr, nullptr);
+    st = decode_core<MAXM, false>(I, l, gp, A.obj_out + i, &work, nullptr, nullptr, span_max);
   }
   if (st == kDecOk) {
     if (__lane_id() == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
@@ -1049,7 +1066,7 @@ __device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
 // One generation of every active slot. ISLAND: an item is an island (its
 // slots in turn, then its replacement); otherwise an item is one child.
 template <int MAXM, bool ISLAND>
-__global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B) {
+__global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B, int cls) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = B.rows * B.cols;
   const int per_slot = ISLAND ? B.islands : B.pop;
@@ -1058,7 +1075,7 @@ __global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B) {
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int d = item / per_slot;
     const BatchSlot S = ld_const_struct(B.slots + d);
-    if (!S.active) continue;
+    if (!S.active || S.cls != cls) continue;
     const int gen = S.gen + 1;
     const GaDev A = slot_ga(S, B, gen);
     const Lds l = carve_lds(smem, S.I.n, MAXM);
@@ -1091,8 +1108,25 @@ __global__ __launch_bounds__(64) void batch_init_kernel(BatchArgs B, int d) {
   const GlobalProfile gp{B.gprof + B.gstride * blockIdx.x, S.I.horizon};
   for (int i = blockIdx.x; i < B.pop; i += gridDim.x) {
     init_child(A0, S.I.n, i, l);
-    decode_slot<MAXM>(S.I, A0, i, S.cap, l, gp);
+    decode_slot<MAXM>(S.I, A0, i, S.cap, l, gp, &B.slots[d].span);
   }
+}
+
+// Profile size class of slot d from its generation 0: the smallest of
+// caps[0..n_cls) that holds 5/4 of the longest schedule plus 64 slots (the
+// largest otherwise), no more than the slot's horizon needs.
+__global__ __launch_bounds__(64) void batch_class_kernel(BatchArgs B, int d, int n_cls, int top) {
+  if (threadIdx.x != 0) return;
+  BatchSlot *S = B.slots + d;
+  const int need = S->span + S->span / 4 + 64;
+  int c = 0, cap = top >> (n_cls - 1);
+  while (c + 1 < n_cls && cap < need) {
+    ++c;
+    cap <<= 1;
+  }
+  const int h = (S->I.horizon + 63) / 64 * 64;
+  S->cls = c;
+  S->cap = cap < h ? cap : h;
 }
 
 __global__ __launch_bounds__(256) void batch_replace_kernel(BatchArgs B) {
@@ -1791,9 +1825,14 @@ BatchLayout batch_layout(void *ws, const ffs_batch_params *p) {
   return L;
 }
 
+int batch_classes(const ffs_batch_params *p) {
+  return p->profile_classes > 1 ? p->profile_classes : 1;
+}
+
 int check_batch_params(const ffs_batch_params *p) {
   if (!p || p->n_slots < 1 || p->max_jobs < 1 || p->max_genes < 1 || p->max_stages < 1 ||
-      p->o_max < 1 || p->max_horizon < 1 || p->blocks < 0 ||
+      p->o_max < 1 || p->max_horizon < 1 || p->blocks < 0 || p->profile_classes < 0 ||
+      p->profile_classes > FFS_BATCH_MAX_CLASSES ||
       (p->schedule != FFS_SCHEDULE_CHROMOSOME && p->schedule != FFS_SCHEDULE_ISLAND))
     return FFS_E_INVAL;
   int rc = check_ga_params(&p->ga);
@@ -1804,11 +1843,14 @@ int check_batch_params(const ffs_batch_params *p) {
   return FFS_OK;
 }
 
+// On-chip profile slots of the largest class: a multiple of 64 << (classes - 1)
+// so that every class (cap >> k) is a multiple of 64.
 int batch_cap(const ffs_batch_params *p) {
+  const size_t unit = (size_t)64 << (batch_classes(p) - 1);
   int cap = p->ga.lds_slots > 0 ? p->ga.lds_slots : kDefaultLdsSlots;
-  cap = (int)align_up((size_t)(cap < 64 ? 64 : cap), 64);
-  if (cap > (int)align_up((size_t)p->max_horizon, 64)) cap = (int)align_up((size_t)p->max_horizon, 64);
-  return cap;
+  cap = (int)align_up((size_t)(cap < 64 ? 64 : cap), unit);
+  const int h = (int)align_up((size_t)p->max_horizon, unit);
+  return cap > h ? h : cap;
 }
 
 BatchArgs batch_args(const ffs_batch *b, const BatchLayout &L) {
@@ -1832,19 +1874,22 @@ BatchArgs batch_args(const ffs_batch *b, const BatchLayout &L) {
 template <int MAXM>
 int batch_generation_launches(const ffs_batch *b, const BatchArgs &B, hipStream_t s, bool timed) {
   const ffs_batch_params &p = b->params;
-  const size_t shmem = lds_bytes(p.max_genes, b->lds_slots, MAXM);
   const int K = p.ga.rows * p.ga.cols;
   const int isl_total = p.n_slots * p.ga.islands;
-  hipError_t e;
-  if (p.schedule == FFS_SCHEDULE_ISLAND) {
-    e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, true>, dim3(b->blocks), dim3(kWave),
-               shmem, s, B);
-  } else {
-    e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, false>, dim3(b->blocks), dim3(kWave),
-               shmem, s, B);
-    if (e == hipSuccess)
-      e = launch(-1, batch_replace_kernel, dim3(isl_total), dim3(256), 0, s, B);
+  const int n_cls = batch_classes(&p);
+  hipError_t e = hipSuccess;
+  // one launch per profile size class, each with that class's LDS
+  for (int c = 0; c < n_cls && e == hipSuccess; ++c) {
+    const size_t shmem = lds_bytes(p.max_genes, b->lds_slots >> (n_cls - 1 - c), MAXM);
+    if (p.schedule == FFS_SCHEDULE_ISLAND)
+      e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, true>, dim3(b->blocks), dim3(kWave),
+                 shmem, s, B, c);
+    else
+      e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, false>, dim3(b->blocks),
+                 dim3(kWave), shmem, s, B, c);
   }
+  if (e == hipSuccess && p.schedule != FFS_SCHEDULE_ISLAND)
+    e = launch(-1, batch_replace_kernel, dim3(isl_total), dim3(256), 0, s, B);
   if (e == hipSuccess && p.ga.mig_interval > 0 && p.ga.mig_k > 0 && p.ga.islands > 1) {
     e = launch(-1, batch_migrate_collect_kernel, dim3(isl_total), dim3(256), (size_t)K, s, B);
     if (e == hipSuccess)
@@ -1884,7 +1929,9 @@ int batch_init_launch(const ffs_batch *b, const BatchArgs &B, int slot, const Ba
   const ffs_batch_params &p = b->params;
   const size_t shmem = lds_bytes(p.max_genes, b->lds_slots, MAXM);
   const int grid = b->pop < b->blocks ? b->pop : b->blocks;
-  if (launch(-1, batch_init_kernel<MAXM>, dim3(grid), dim3(kWave), shmem, s, B, slot) != hipSuccess)
+  if (launch(-1, batch_init_kernel<MAXM>, dim3(grid), dim3(kWave), shmem, s, B, slot) != hipSuccess ||
+      launch(-1, batch_class_kernel, dim3(1), dim3(kWave), 0, s, B, slot, batch_classes(&p),
+             b->lds_slots) != hipSuccess)
     return FFS_E_DEVICE;
   uint8_t *base = L.slot_base + L.slot_stride * slot;
   const int n = b->n_genes[slot];

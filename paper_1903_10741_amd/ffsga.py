@@ -388,6 +388,7 @@ def exported_symbols():
 FFS_SCHEDULE_CHROMOSOME = 0
 FFS_SCHEDULE_ISLAND = 1
 FFS_BATCH_MAX_SLOTS = 4096
+FFS_BATCH_MAX_CLASSES = 4
 
 
 class FfsBatchParams(ctypes.Structure):
@@ -395,7 +396,7 @@ class FfsBatchParams(ctypes.Structure):
         ("n_slots", ctypes.c_int32), ("max_jobs", ctypes.c_int32), ("max_genes", ctypes.c_int32),
         ("max_stages", ctypes.c_int32), ("o_max", ctypes.c_int32), ("max_horizon", ctypes.c_int32),
         ("ga", FfsGaParams), ("schedule", ctypes.c_int32), ("blocks", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("profile_classes", ctypes.c_int32),
     ]
 
 
@@ -440,11 +441,12 @@ class BatchConfig:
     schedule: int = FFS_SCHEDULE_CHROMOSOME
     blocks: int = 0
     use_graph: bool = False
+    profile_classes: int = 1
 
     def c(self):
         return FfsBatchParams(self.n_slots, self.max_jobs, self.max_genes, self.max_stages,
                               self.o_max, self.max_horizon, self.ga.c(), self.schedule,
-                              self.blocks, 1 if self.use_graph else 0)
+                              self.blocks, 1 if self.use_graph else 0, self.profile_classes)
 
     def workspace_bytes(self) -> int:
         """Device bytes a batch of this shape needs (ffs_batch_workspace_size)."""

@@ -180,7 +180,8 @@ class Server:
             o_max=max(int(i.o_max) for i in instances), max_horizon=int(max_horizon),
             ga=ffsga.GaConfig.of(ga, lds_slots=tuning.get("lds_slots", 0)),
             schedule=tuning.get("schedule", ffsga.FFS_SCHEDULE_CHROMOSOME),
-            blocks=tuning.get("blocks", 0), use_graph=tuning.get("use_graph", True))
+            blocks=tuning.get("blocks", 0), use_graph=tuning.get("use_graph", True),
+            profile_classes=tuning.get("profile_classes", 1))
         # the most slots whose workspace fits the memory budget
         fit = int(n_slots)
         if memory_budget is not None:

@@ -43,13 +43,13 @@ def _instances():
     return out
 
 
-def _batch(ffsga, insts, schedule, use_graph, blocks=7, lds_slots=0, n_slots=None):
+def _batch(ffsga, insts, schedule, use_graph, blocks=7, lds_slots=0, n_slots=None, classes=1):
     cfg = ffsga.BatchConfig(
         n_slots=n_slots or len(insts), max_jobs=max(i.n_jobs for i in insts),
         max_genes=max(i.n_active for i in insts), max_stages=max(i.n_stages for i in insts),
         o_max=4, max_horizon=max(oracle.horizon_bound(i) for i in insts),
         ga=ffsga.GaConfig.of(GA, lds_slots=lds_slots), schedule=schedule, blocks=blocks,
-        use_graph=use_graph)
+        use_graph=use_graph, profile_classes=classes)
     return ffsga.Batch(cfg)
 
 
@@ -152,6 +152,24 @@ def test_batch_off_chip_redo(schedule):
         _same(_state(b, s), oracle.ga_run(i, GA, 3, s, 0, 4), f"slot {s}")
 
 
+@pytest.mark.parametrize("schedule,use_graph", [(0, True), (1, False)])
+def test_batch_profile_classes(schedule, use_graph):
+    """Profile size classes 64/128/256 slots: slots of different schedule lengths
+    land in different class launches (and long ones still overflow off chip);
+    every slot stays bit-exact."""
+    torch, ffsga = _ffs()
+    _say("batch with profile classes, schedule", schedule, "graph", use_graph)
+    insts = _instances()
+    dev = [ffsga.DeviceInstance.from_host(i) for i in insts]
+    b = _batch(ffsga, insts, schedule, use_graph, lds_slots=256, classes=3)
+    for s, d in enumerate(dev):
+        b.set(s, d, 12, s, 1)
+    b.step(5)
+    b.status()
+    for s, i in enumerate(insts):
+        _same(_state(b, s), oracle.ga_run(i, GA, 12, s, 1, 5), f"slot {s}")
+
+
 def test_batch_of_shops_sampled():
     """Forty uneven shops of the serving shape, population 1024 each, in the
     launch shape the benchmark uses: sampled slots against the oracle."""
@@ -160,7 +178,8 @@ def test_batch_of_shops_sampled():
     shops = W.shops(3, 40)
     cfg = ffsga.BatchConfig(n_slots=40, max_jobs=200, max_genes=200, max_stages=10, o_max=6,
                             max_horizon=max(oracle.horizon_bound(s) for s in shops),
-                            ga=ffsga.GaConfig.of(W.SERVING_GA), use_graph=True)
+                            ga=ffsga.GaConfig.of(W.SERVING_GA, lds_slots=16384), use_graph=True,
+                            profile_classes=3)
     b = ffsga.Batch(cfg)
     dev = [ffsga.DeviceInstance.from_host(s) for s in shops]
     for s, d in enumerate(dev):
