@@ -137,26 +137,31 @@ struct LdsProfile {
   __device__ void order() const { __asm__ volatile("" ::: "memory"); }
 };
 
-// Profile with one byte per slot in global memory (overflow tier).
+// Profile with one byte per slot in global memory (overflow tier). Each
+// profile belongs to one single-wave block, so work-group scope orders the
+// lanes' updates and reads; nothing else touches it.
 struct GlobalProfile {
   uint8_t *p;
   int cap;
   __device__ void clear() const {
     uint32_t *w = (uint32_t *)p;
     for (int x = __lane_id(); x < (cap + kWave) / 4; x += kWave)
-      __hip_atomic_store(w + x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+      __hip_atomic_store(w + x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    order();
   }
   __device__ uint32_t get(int x) const {
     uint32_t w = __hip_atomic_load((uint32_t *)(p + (x & ~3)), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     return (w >> (8 * (x & 3))) & 0xFFu;
   }
   __device__ void add(int x, uint32_t q) const {
-    atomicAdd((uint32_t *)(p + (x & ~3)), q << (8 * (x & 3)));
+    __hip_atomic_fetch_add((uint32_t *)(p + (x & ~3)), q << (8 * (x & 3)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __device__ void add_word(int x4, uint32_t w) const { atomicAdd((uint32_t *)(p + x4), w); }
-  __device__ void order() const { __threadfence(); }
+  __device__ void add_word(int x4, uint32_t w) const {
+    __hip_atomic_fetch_add((uint32_t *)(p + x4), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ void order() const { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
 };
 
 enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
