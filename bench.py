@@ -68,7 +68,12 @@ def bench_batch(args):
     gens = args.generations or 100
     dev = [ffsga.DeviceInstance.from_host(s) for s in shops]
     horizon = max(d.horizon for d in dev)
-    tune = autotune.tune(dev, shops, ga, generations=2, log=progress)
+    if args.no_autotune:
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        tune = autotune.TuneResult(autotune.Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, 8192, 8 * n_cu,
+                                                      True, 3), float("nan"), [])
+    else:
+        tune = autotune.tune(dev, shops, ga, generations=2, log=progress)
     cfg = autotune.batch_config(shops, ga, horizon, tune.best)
     b = ffsga.Batch(cfg)
 
@@ -300,6 +305,9 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--race-seeds", type=int, default=8)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch: the usual tuned configuration (8192 profile slots in 3 classes, "
+                         "8 blocks per CU, one wave per child, graph) without tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
