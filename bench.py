@@ -127,6 +127,58 @@ def bench_batch(args):
     return out
 
 
+def bench_large(args):
+    """Large decode throughput: event 0 of large-200x10x4-6 (200 jobs, 10 stages, 4-6
+    unrelated machines, population 65536 = 512 islands x 8x16) for 200 generations in
+    the batched launch, one slot; the autotuner times one wave per child against one
+    wave per island (and the on-chip profile sizes) and the step runs the faster."""
+    import torch
+    from paper_1903_10741_amd import autotune, ffsga
+    from paper_1903_10741_amd import workloads as W
+    wl = W.config3(args.seed)
+    gens = args.generations or wl.generations
+    inst = wl.initial
+    dev = [ffsga.DeviceInstance.from_host(inst)]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cands = []
+    for lds in (8192, 16384):
+        for sched, blocks in ((ffsga.FFS_SCHEDULE_CHROMOSOME, 8 * n_cu),
+                              (ffsga.FFS_SCHEDULE_CHROMOSOME, 16 * n_cu),
+                              (ffsga.FFS_SCHEDULE_ISLAND, 2 * n_cu),
+                              (ffsga.FFS_SCHEDULE_ISLAND, 4 * n_cu)):
+            cands.append(autotune.Candidate(sched, lds, blocks, True))
+    tune = autotune.tune(dev, [inst], wl.ga, candidates=cands, generations=2, log=progress)
+    b = ffsga.Batch(autotune.batch_config([inst], wl.ga, dev[0].horizon, tune.best))
+
+    def one_step():
+        b.set(0, dev[0], args.seed, 0, 0)
+        b.step(gens)
+    for _ in range(args.warmup):
+        one_step()
+    b.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step()
+        b.stream.synchronize()
+        progress(f"large step {k + 1} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    b.status()
+    decodes = wl.ga.pop * (1 + gens)
+    best = {s: min(r["us_per_generation"] for r in tune.table if r["schedule"] == s)
+            for s in (ffsga.FFS_SCHEDULE_CHROMOSOME, ffsga.FFS_SCHEDULE_ISLAND)}
+    out = common(args, "exact chromosome decodes/sec", decodes * args.steps / elapsed, "decodes/s",
+                 elapsed * 1e3 / args.steps, "int32", {
+                     "workload": f"large-200x10x4-6 event 0: 200 jobs, 10 stages, 4-6 unrelated "
+                                 f"machines, 512 islands x 8x16 = 65536, {gens} generations",
+                     "decodes_per_step": decodes, "autotuned": tune.best.__dict__,
+                     "us_per_generation_wave_per_child": best[ffsga.FFS_SCHEDULE_CHROMOSOME],
+                     "us_per_generation_wave_per_island": best[ffsga.FFS_SCHEDULE_ISLAND],
+                     "tuning_table": tune.table})
+    return out
+
+
 def bench_serve(args):
     """Rescheduling requests from 512 shops arriving Poisson at 200/s, each 100
     generations of population 1024, continuously batched; latency and throughput."""
@@ -294,7 +346,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper", choices=["paper", "batch", "serve", "surrogate"])
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "batch", "serve", "surrogate", "large"])
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -326,6 +379,9 @@ def main():
         return
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args)), flush=True)
+        return
+    if args.workload == "large":
+        print(json.dumps(bench_large(args)), flush=True)
         return
     bench_paper(args)
 
