@@ -123,7 +123,8 @@ def bench_batch(args):
                        "peak": VALU_INT32_PEAK_TOPS, "unit": "TOP/s int32",
                        "frac": achieved / VALU_INT32_PEAK_TOPS, "traffic": None,
                        "avg_launch_us": avg * 1e6, "launches": launches,
-                       "work_per_decode": work / max(len(shops) * ga.pop * min(gens, 10), 1)}
+                       "work_per_decode": work / max(len(shops) * ga.pop * min(gens, 10), 1),
+                       "build_id": ffsga.ffs_build_id()}
     return out
 
 
