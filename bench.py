@@ -38,9 +38,23 @@ def cpu_baseline(wl):
                             n_threads=threads)
     dt = time.perf_counter() - t0
     decodes = len(out) * ((1 + wl.generations) * wl.ga.pop + 1)
+    # one thread, on a bounded sample: event 0, generation 0 and 4 generations
+    t1 = time.perf_counter()
+    oracle.ga_run(wl.initial, wl.ga, wl.seed, wl.shop, 0, 4, n_threads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                     if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": decodes / dt, "unit": "decodes/s", "cores": threads, "kind": "oracle",
             "sample": f"one full step: {len(out)} events x (1 + {wl.generations}) generations x "
                       f"{wl.ga.pop} individuals + plan decodes ({decodes} decodes, {dt:.1f} s)",
+            "single_thread": {"value": 5 * wl.ga.pop / dt1, "unit": "decodes/s", "cores": 1,
+                              "sample": f"event 0, generation 0 + 4 generations ({5 * wl.ga.pop} "
+                                        f"decodes, {dt1:.1f} s)"},
+            "nproc": os.cpu_count(), "cpu_model": model,
             "best_obj_per_event": [int(e["best_obj"]) for e in out]}
 
 
@@ -181,15 +195,18 @@ def bench_large(args):
 
 
 def bench_serve(args):
-    """Rescheduling requests from 512 shops arriving Poisson at 200/s, each 100
-    generations of population 1024, continuously batched; latency and throughput."""
+    """Rescheduling requests from 512 shops arriving Poisson at 200/s: each request
+    is one arrival event (U{5..10} new jobs) of a shop whose first plan exists,
+    rescheduled and then 100 generations of population 1024, continuously
+    batched; latency and throughput. The first plans are made beforehand through
+    the same path and not counted."""
     import torch
     from paper_1903_10741_amd import autotune, ffsga
     from paper_1903_10741_amd import workloads as W
     from paper_1903_10741_amd.serve import Server, poisson_schedule
-    n_events = 2
+    n_arrivals = 2
     shops = W.shops(args.seed, args.shops)
-    arrs = [W.shop_arrivals(args.seed, k, s, n_events - 1) for k, s in enumerate(shops)]
+    arrs = [W.shop_arrivals(args.seed, k, s, n_arrivals) for k, s in enumerate(shops)]
     gens = args.generations or 100
     dev = [ffsga.DeviceInstance.from_host(s) for s in shops[:64]]
     tune = autotune.tune(dev, shops[:64], W.SERVING_GA, generations=2, log=progress)
@@ -198,35 +215,22 @@ def bench_serve(args):
                  tuning={"use_graph": True, "blocks": tune.best.blocks,
                          "lds_slots": tune.best.lds_slots, "schedule": tune.best.schedule,
                          "profile_classes": tune.best.profile_classes})
-    progress("serving starts")
-    sched = poisson_schedule(args.seed, args.rate, [n_events] * len(shops))
+    progress("first plans")
+    first = srv.prime()
+    progress(f"first plans done in {first['wall_s']:.1f} s; serving starts")
+    sched = poisson_schedule(args.seed, args.rate, [n_arrivals] * len(shops))
     torch.cuda.synchronize()
     m = srv.run(sched, log=progress)
     out = common(args, "exact chromosome decodes/sec", m["decodes_per_s"], "decodes/s",
                  m["wall_s"] * 1e3, "int32", {
-                     "workload": f"serving: {len(shops)} shops, {n_events} events each, Poisson "
-                                 f"{args.rate}/s, {gens} generations x pop 1024 per request",
+                     "workload": f"serving: {len(shops)} shops, {n_arrivals} arrival requests each "
+                                 f"(U{{5..10}} jobs), Poisson {args.rate}/s, {gens} generations x "
+                                 f"pop 1024 per request",
+                     "first_plans_s": first["wall_s"],
                      **{k: v for k, v in m.items()}})
     out["steps"] = 1
     out["warmup"] = 0
     return out
-
-
-def surrogate_dataset(d, ga_cfg, seeds, gens):
-    """Decoder-labelled chromosomes: every population of `gens` plain generations
-    (and generation 0) of GA runs with the given seeds, with their exact objectives."""
-    import torch
-    from paper_1903_10741_amd import ffsga
-    prios, objs = [], []
-    for sd in seeds:
-        g = ffsga.GA(d, ga_cfg, sd, 0, 0)
-        for k in range(gens + 1):
-            if k:
-                g.step(1)
-            v = g.view()
-            prios.append(v["prio"].clone())
-            objs.append(v["obj"].clone())
-    return torch.cat(prios), torch.cat(objs)
 
 
 def spearman(a, b):
@@ -236,55 +240,61 @@ def spearman(a, b):
     return float(np.corrcoef(ra, rb)[0, 1])
 
 
+def populations(d, ga_cfg, seed, snap_gens):
+    """Decoder-labelled chromosomes: the populations of one plain GA run at the given
+    generations (0 = the initial population), with their exact objectives."""
+    import torch
+    from paper_1903_10741_amd import ffsga
+    g = ffsga.GA(d, ga_cfg, seed, 0, 0)
+    prios, objs, done = [], [], 0
+    for k in snap_gens:
+        if k > done:
+            g.step(k - done)
+            done = k
+        v = g.view()
+        prios.append(v["prio"].clone())
+        objs.append(v["obj"].clone())
+    return torch.cat(prios), torch.cat(objs)
+
+
 def bench_surrogate(args):
-    """Time to reach the plain GA's final fitness (500 generations, event 0 of the
-    paper-shaped workload), screened GA (4 candidates per cell, lowest surrogate
-    score kept) against the plain GA, same seed, same GPU."""
+    """Time to reach the plain GA's final fitness, screened GA (4 candidates per cell,
+    the lowest surrogate score kept) against the plain GA, on paper-shaped event-0
+    instances of seeds 0..race_seeds-1, same GA seed, 500 generations each; per
+    instance the speedup is the plain GA's time to reach its own final objective
+    over the screened GA's time to reach it, and the value is the median.
+
+    Per instance (the value): the network is trained on 2.03 M decoder-labelled
+    chromosomes of that instance (the populations of 16 seeded plain-GA runs,
+    generations 0-30), 2 epochs of Adam; data and training time are reported
+    apart. Across instances (reported beside it): one network trained on
+    instances of seeds 100-199 (generations 0, 10, 20, 40, 80 of one run each,
+    2.05 M chromosomes) and raced on the same unseen instances."""
     import numpy as np
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
-    wl = W.config2(args.seed)
-    inst = wl.initial
-    gens = args.generations or wl.generations
-    cfg = ffsga.GaConfig.of(wl.ga)
-    d = ffsga.DeviceInstance.from_host(inst)
-    # 1. data: 16 seeded runs x 31 populations x 4096 = 2.03M decoder-labelled chromosomes
-    t0 = time.perf_counter()
-    prio, obj = surrogate_dataset(d, cfg, range(1000, 1016), 30)
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    # 2. training: Adam, batches of 4096, 2 epochs, constant rate; targets standardised
-    #    within each population
-    model = ffsga.Surrogate(W.surrogate_init(args.seed))
-    feats = model.features(d)
-    tgt = model.targets(obj, wl.ga.pop)
-    gen = torch.Generator(device="cpu").manual_seed(args.seed)
-    N = prio.shape[0]
+    base = W.config2(0)
+    gens = args.generations or base.generations
+    cfg = ffsga.GaConfig.of(base.ga)
+    pop = base.ga.pop
     B = 4096
-    t0 = time.perf_counter()
-    losses = []
-    for ep in range(2):
-        perm = torch.randperm(N, generator=gen).cuda()
-        for i in range(0, N - B + 1, B):
-            idx = perm[i:i + B]
-            loss, _ = model.train_step(feats, prio[idx], tgt[idx], 1e-3)
-            losses.append(loss)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    losses = [float(x.item()) for x in losses]
-    table = model.score_table(feats, inst.n_active)
-    # held-out quality: rank correlation inside populations of an unseen seed
-    ho_p, ho_o = surrogate_dataset(d, cfg, [7777], 20)
-    ys = model.score(table, ho_p).cpu().numpy()
-    ho = ho_o.cpu().numpy()
-    rho = [spearman(ys[k * wl.ga.pop:(k + 1) * wl.ga.pop], ho[k * wl.ga.pop:(k + 1) * wl.ga.pop])
-           for k in (0, 10, 20)]
+    gen = torch.Generator(device="cpu").manual_seed(args.seed)
 
-    # 3. the race, per seed: plain and screened GA for the same generations, best
-    #    elite read every 10 generations; the time each first reaches the plain
-    #    GA's final objective
-    def race(seed, screened):
+    def train(model, data):
+        n_pairs = sum(int(x[1].shape[0]) for x in data)
+        steps = 2 * n_pairs // B
+        losses = []
+        for _ in range(steps):
+            i = int(torch.randint(len(data), (1,), generator=gen))
+            feats, prio, tgt = data[i]
+            idx = torch.randint(prio.shape[0], (B,), generator=gen).cuda()
+            losses.append(model.train_step(feats, prio[idx], tgt[idx], 1e-3)[0])
+        torch.cuda.synchronize()
+        losses = [float(x.item()) for x in losses]
+        return steps, losses[0], float(np.mean(losses[-50:]))
+
+    def race(model, d, table, seed, screened):
         g = ffsga.GA(d, cfg, seed, 0, 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -304,39 +314,84 @@ def bench_surrogate(args):
 
     def first(trace, target):
         return next(((gn, t) for gn, t, b in trace if b <= target), (None, None))
-    race(0, False)    # warm-up of both paths
-    race(0, True)
-    per_seed = []
-    for sd in range(args.seed, args.seed + args.race_seeds):
-        plain, scr = race(sd, False), race(sd, True)
+
+    def evaluate(model, d, sd, plain, tag):
+        table = model.score_table(model.features(d), d.n_active)
+        hp, ho = populations(d, cfg, 7777 + sd, (0, 20))
+        ys = model.score(table, hp).cpu().numpy()
+        ho = ho.cpu().numpy()
+        rho = [spearman(ys[k * pop:(k + 1) * pop], ho[k * pop:(k + 1) * pop]) for k in (0, 1)]
+        scr = race(model, d, table, sd, True)
         target = plain[-1][2]
         gp, tp = first(plain, target)
         gs, ts = first(scr, target)
-        per_seed.append({"seed": sd, "plain_final": target, "screened_final": scr[-1][2],
-                         "plain_gens_to_target": gp, "plain_s_to_target": tp,
-                         "screened_gens_to_target": gs, "screened_s_to_target": ts,
-                         "speedup": (tp / ts) if ts else None,
-                         "plain_s_per_gen": plain[-1][1] / plain[-1][0],
-                         "screened_s_per_gen": scr[-1][1] / scr[-1][0]})
-        print(f"[bench] race seed {sd}: plain {target} at gen {gp}, screened {scr[-1][2]}, "
-              f"reached at gen {gs}", file=sys.stderr, flush=True)
-    sp = [r["speedup"] if r["speedup"] is not None else 0.0 for r in per_seed]
-    value = float(np.median(sp))
-    out = common(args, "time-to-equal-fitness, surrogate vs plain GA", value,
+        progress(f"{tag} instance {sd}: plain {target} at gen {gp}, screened {scr[-1][2]}, "
+                 f"reached at gen {gs}, rank correlation {rho[0]:.2f}/{rho[1]:.2f}")
+        return {"instance_seed": sd, "plain_final": target, "screened_final": scr[-1][2],
+                "plain_gens_to_target": gp, "plain_s_to_target": tp,
+                "screened_gens_to_target": gs, "screened_s_to_target": ts,
+                "speedup": (tp / ts) if ts else None, "heldout_spearman_gen0_20": rho,
+                "plain_s_per_gen": plain[-1][1] / plain[-1][0],
+                "screened_s_per_gen": scr[-1][1] / scr[-1][0]}
+
+    def summary(rows):
+        sp = [r["speedup"] if r["speedup"] is not None else 0.0 for r in rows]
+        return {"median_speedup": float(np.median(sp)),
+                "reached": sum(r["screened_s_to_target"] is not None for r in rows),
+                "screened_better_final": sum(r["screened_final"] < r["plain_final"] for r in rows),
+                "per_instance": rows}
+
+    # the cross-instance network: trained once on instances 100..
+    t0 = time.perf_counter()
+    cross = ffsga.Surrogate(W.surrogate_init(args.seed))
+    data = []
+    for sd in range(100, 100 + args.train_instances):
+        d = ffsga.DeviceInstance.from_host(W.config2(sd).initial)
+        prio, obj = populations(d, cfg, sd, (0, 10, 20, 40, 80))
+        data.append((cross.features(d), prio, cross.targets(obj, pop)))
+    cross_pairs = sum(int(x[1].shape[0]) for x in data)
+    cross_fit = train(cross, data)
+    del data
+    t_cross = time.perf_counter() - t0
+    progress(f"cross-instance network: {cross_pairs} pairs, {cross_fit[0]} steps, "
+             f"loss {cross_fit[1]:.3f} -> {cross_fit[2]:.3f}, {t_cross:.1f} s")
+    own_rows, cross_rows, prep = [], [], []
+    for sd in range(args.seed, args.seed + args.race_seeds):
+        d = ffsga.DeviceInstance.from_host(W.config2(sd).initial)
+        t0 = time.perf_counter()
+        model = ffsga.Surrogate(W.surrogate_init(args.seed))
+        feats = model.features(d)
+        data = []
+        for rs in range(1000, 1016):
+            prio, obj = populations(d, cfg, rs, tuple(range(31)))
+            data.append((feats, prio, model.targets(obj, pop)))
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        fit = train(model, data)
+        del data
+        t_prep = time.perf_counter() - t0
+        prep.append({"instance_seed": sd, "data_s": t_data, "train_s": t_prep - t_data,
+                     "steps": fit[0], "loss_first": fit[1], "loss_last50": fit[2]})
+        if sd == args.seed:   # warm-up of both paths
+            race(model, d, None, sd, False)
+            race(model, d, model.score_table(feats, d.n_active), sd, True)
+        plain = race(model, d, None, sd, False)
+        own_rows.append(evaluate(model, d, sd, plain, "own-instance network"))
+        cross_rows.append(evaluate(cross, d, sd, plain, "cross-instance network"))
+    own, crs = summary(own_rows), summary(cross_rows)
+    out = common(args, "time-to-equal-fitness, surrogate vs plain GA", own["median_speedup"],
                  "x (plain GA time / screened GA time to the plain GA's final objective)",
-                 sum(r["plain_s_per_gen"] + r["screened_s_per_gen"] for r in per_seed) * gens * 1e3,
+                 sum(r["plain_s_per_gen"] + r["screened_s_per_gen"] for r in own_rows) * gens * 1e3,
                  "bf16/fp32 surrogate, int32 decode", {
-                     "workload": "paper-shaped event 0 (50 jobs, 5 stages, 3 machines), "
-                                 f"32 islands x 8x16, {gens} generations, screened: 4 candidates "
-                                 f"per cell, {args.race_seeds} seeds (median speedup; a seed whose "
-                                 "screened run never reaches the target counts 0)",
-                     "seeds_reached": sum(r["screened_s_to_target"] is not None for r in per_seed),
-                     "screened_better_final": sum(r["screened_final"] < r["plain_final"]
-                                                  for r in per_seed),
-                     "per_seed": per_seed,
-                     "train_pairs": int(N), "train_steps": len(losses), "train_s": t_train,
-                     "data_s": t_data, "loss_first": losses[0], "loss_last": losses[-1],
-                     "heldout_spearman_gen0_10_20": rho})
+                     "workload": "paper-shaped event 0 (50 jobs, 5 stages, 3 machines), 32 islands "
+                                 f"x 8x16, {gens} generations, screened: 4 candidates per cell; "
+                                 f"instances {args.seed}-{args.seed + args.race_seeds - 1}; value: "
+                                 "median over instances of the own-instance network's speedup (0 "
+                                 "where the screened run never reaches the target)",
+                     "own_instance": {**own, "training": prep},
+                     "cross_instance": {**crs, "train_pairs": cross_pairs, "train_steps": cross_fit[0],
+                                        "loss_first": cross_fit[1], "loss_last50": cross_fit[2],
+                                        "data_and_train_s": t_cross}})
     out["steps"] = 1
     out["warmup"] = 1
     return out
@@ -358,7 +413,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--gens-per-tick", type=int, default=10)
-    ap.add_argument("--race-seeds", type=int, default=8)
+    ap.add_argument("--race-seeds", type=int, default=10)
+    ap.add_argument("--train-instances", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch: the usual tuned configuration (8192 profile slots in 3 classes, "
                          "8 blocks per CU, one wave per child, graph) without tuning")
@@ -428,11 +484,13 @@ def bench_paper(args):
 
     value = decodes / elapsed
     traffic = None
+    valu_issue = None
     tpath = os.path.join(ROOT, "profiles", "ga_generation_kernel_paper-50x5x3.traffic.json")
     if os.path.exists(tpath):
         t = json.load(open(tpath))
         if t.get("build_id") == ffsga.ffs_build_id():  # counters of this very build only
             traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+            valu_issue = t.get("valu_issue_tlops")
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
     decodes_per_launch = wl.ga.pop
     achieved = work_per_decode * decodes_per_launch / avg_launch_s / 1e12
@@ -464,6 +522,7 @@ def bench_paper(args):
             "unit": "TOP/s int32",
             "frac": achieved / VALU_INT32_PEAK_TOPS,
             "traffic": traffic,
+            "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
             "work_per_decode": work_per_decode,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": gen_launches,

@@ -36,7 +36,10 @@ constexpr int kB3 = 7 * H + H * H;      // [1]
 static_assert(kB3 + 1 == FFS_SG_PARAMS, "parameter layout");
 
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // LDS row stride in bf16 elements
-constexpr int kChunk = 256;                               // table rows per dW2 / db2 partial
+constexpr int kChunk = 256;                               // table rows per dW2 partial
+constexpr int kRowChunk = 32;                             // table rows per db2 partial
+constexpr int kBatchChunk = 64;                           // chromosomes per head partial
+constexpr int kDChunk = 256;                              // chromosomes per D partial
 constexpr int kHeaderBytes = 256;  // head of the training workspace: status word first, as ffs_status reads it
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -334,42 +337,65 @@ __global__ __launch_bounds__(64) void batch_fwd_kernel(const float *theta, const
   }
 }
 
-// D[k][v-1] = sum of dy_b over the chromosomes whose gene k is v, b in order.
-// grid n (one block per gene position), dynamic LDS B ints + B floats.
+// Partials of D[k][v-1] = sum of dy_b over the chromosomes whose gene k is v:
+// block (k, c) sums chromosomes [c * kDChunk, (c + 1) * kDChunk) in b order into
+// part[c][k * n + v - 1]; the chunks are then added in chunk order.
 __global__ __launch_bounds__(256) void dtable_kernel(const int32_t *prio, const float *dy, int n,
-                                                     int B, float *D, const int32_t *status) {
+                                                     int B, float *part, const int32_t *status) {
   if (status[0]) return;
-  extern __shared__ __align__(16) uint8_t smem[];
-  int32_t *vals = (int32_t *)smem;
-  float *dys = (float *)(smem + (size_t)B * 4);
-  const int k = blockIdx.x;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    vals[b] = prio[(size_t)b * n + k];
-    dys[b] = dy[b];
+  __shared__ int32_t vals[kDChunk];
+  __shared__ float dys[kDChunk];
+  const int k = blockIdx.x, c = blockIdx.y;
+  const int b0 = c * kDChunk, nb = B - b0 < kDChunk ? B - b0 : kDChunk;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    vals[i] = prio[(size_t)(b0 + i) * n + k];
+    dys[i] = dy[b0 + i];
   }
   __syncthreads();
   for (int v = threadIdx.x + 1; v <= n; v += blockDim.x) {
     float s = 0.f;
-    for (int b = 0; b < B; ++b)
-      if (vals[b] == v) s += dys[b];
-    D[k * n + v - 1] = s;
+    for (int i = 0; i < nb; ++i)
+      if (vals[i] == v) s += dys[i];
+    part[(size_t)c * n * n + k * n + v - 1] = s;
   }
 }
 
-// dw3, db3 and the loss: sums over the batch in b order.
+// Partials of dw3, db3 and the loss over chromosomes [c * kBatchChunk, ...),
+// b in order: part[c][0..H) = dw3, part[c][H] = db3, part[c][H + 1] = sum of squares.
 __global__ __launch_bounds__(256) void head_kernel(const float *dy, const float *z, const float *sq,
-                                                   int B, float *grad, float *loss,
-                                                   const int32_t *status) {
+                                                   int B, float *part, const int32_t *status) {
+  if (status[0]) return;
+  const int o = threadIdx.x, c = blockIdx.x;
+  const int b0 = c * kBatchChunk, b1 = b0 + kBatchChunk < B ? b0 + kBatchChunk : B;
+  float s = 0.f;
+  for (int b = b0; b < b1; ++b) s += __fmul_rn(dy[b], z[(size_t)b * H + o]);
+  float *out = part + (size_t)c * (H + 2);
+  out[o] = s;
+  if (o == 0) {
+    float d = 0.f, l = 0.f;
+    for (int b = b0; b < b1; ++b) {
+      d += dy[b];
+      l += sq[b];
+    }
+    out[H] = d;
+    out[H + 1] = l;
+  }
+}
+
+// The head partials added in chunk order: dw3, db3 and the loss (mean of squares).
+__global__ __launch_bounds__(256) void head_sum_kernel(const float *part, int n_parts, int B,
+                                                       float *grad, float *loss,
+                                                       const int32_t *status) {
   if (status[0]) return;
   const int o = threadIdx.x;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += __fmul_rn(dy[b], z[(size_t)b * H + o]);
+  for (int c = 0; c < n_parts; ++c) s += part[(size_t)c * (H + 2) + o];
   grad[kW3 + o] = s;
   if (o == 0) {
     float d = 0.f, l = 0.f;
-    for (int b = 0; b < B; ++b) {
-      d += dy[b];
-      l += sq[b];
+    for (int c = 0; c < n_parts; ++c) {
+      d += part[(size_t)c * (H + 2) + H];
+      l += part[(size_t)c * (H + 2) + H + 1];
     }
     grad[kB3] = d;
     loss[0] = __fdiv_rn(l, (float)B);
@@ -382,9 +408,9 @@ __global__ __launch_bounds__(256) void db2_part_kernel(const float *theta, const
                                                        const int32_t *status) {
   if (status[0]) return;
   const int Q = n * n, c = blockIdx.x, o = threadIdx.x;
-  const int q1 = (c + 1) * kChunk < Q ? (c + 1) * kChunk : Q;
+  const int q1 = (c + 1) * kRowChunk < Q ? (c + 1) * kRowChunk : Q;
   float s = 0.f;
-  for (int q = c * kChunk; q < q1; ++q) s += out_grad(h2, D, theta, q, o, (float)n);
+  for (int q = c * kRowChunk; q < q1; ++q) s += out_grad(h2, D, theta, q, o, (float)n);
   part[(size_t)c * H + o] = s;
 }
 
@@ -538,7 +564,7 @@ TableWs table_ws(void *ws, int n) {
 
 struct TrainWs {
   int32_t *status;
-  float *ctab, *h2, *D, *z, *dy, *sq, *part1, *part_b2, *part_w2, *grad, *loss;
+  float *ctab, *h2, *D, *Dpart, *z, *dy, *sq, *head, *part1, *part_b2, *part_w2, *grad, *loss;
   size_t total;
 };
 
@@ -546,6 +572,8 @@ TrainWs train_ws(void *ws, int n, int B) {
   uint8_t *b = (uint8_t *)ws;
   TrainWs L{};
   const size_t Q = (size_t)n * n, chunks = (Q + kChunk - 1) / kChunk, blocks = (Q + BM - 1) / BM;
+  const size_t rchunks = (Q + kRowChunk - 1) / kRowChunk, dchunks = (B + kDChunk - 1) / kDChunk;
+  const size_t hchunks = (B + kBatchChunk - 1) / kBatchChunk;
   size_t off = kHeaderBytes;
   L.status = (int32_t *)b;
   auto take = [&](size_t floats) {
@@ -556,11 +584,13 @@ TrainWs train_ws(void *ws, int n, int B) {
   L.ctab = take((size_t)n * H);
   L.h2 = take(Q * H);
   L.D = take(Q);
+  L.Dpart = take(dchunks * Q);
   L.z = take((size_t)B * H);
   L.dy = take(B);
   L.sq = take(B);
+  L.head = take(hchunks * (H + 2));
   L.part1 = take(blocks * 5 * H);
-  L.part_b2 = take(chunks * H);
+  L.part_b2 = take(rchunks * H);
   L.part_w2 = take(chunks * H * H);
   L.grad = take(FFS_SG_PARAMS);
   L.loss = take(1);
@@ -645,6 +675,8 @@ int sg_train_step(ffs_surrogate *m, const float *feats, int32_t n, const int32_t
   if (!workspace || workspace_bytes < L.total) return FFS_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int Q = n * n, chunks = (Q + kChunk - 1) / kChunk, blocks = (Q + BM - 1) / BM;
+  const int rchunks = (Q + kRowChunk - 1) / kRowChunk, dchunks = (B + kDChunk - 1) / kDChunk;
+  const int hchunks = (B + kBatchChunk - 1) / kBatchChunk;
   const float *th = m->theta;
   const int32_t *st = L.status;
   hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, s, L.status);
@@ -656,14 +688,18 @@ int sg_train_step(ffs_surrogate *m, const float *feats, int32_t n, const int32_t
                      (float *)nullptr);
   hipLaunchKernelGGL(batch_fwd_kernel, dim3(B), dim3(64), 0, s, th, (const float *)L.h2, prio,
                      target, n, B, L.z, L.dy, L.sq, st);
-  hipLaunchKernelGGL(dtable_kernel, dim3(n), dim3(256), (size_t)B * 8, s, prio,
-                     (const float *)L.dy, n, B, L.D, st);
-  hipLaunchKernelGGL(head_kernel, dim3(1), dim3(256), 0, s, (const float *)L.dy,
-                     (const float *)L.z, (const float *)L.sq, B, L.grad, L.loss, st);
-  hipLaunchKernelGGL(db2_part_kernel, dim3(chunks), dim3(256), 0, s, th, (const float *)L.h2,
+  hipLaunchKernelGGL(dtable_kernel, dim3(n, dchunks), dim3(256), 0, s, prio, (const float *)L.dy,
+                     n, B, L.Dpart, st);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid1(Q)), dim3(256), 0, s, (const float *)L.Dpart,
+                     dchunks, (size_t)Q, Q, L.D, st);
+  hipLaunchKernelGGL(head_kernel, dim3(hchunks), dim3(256), 0, s, (const float *)L.dy,
+                     (const float *)L.z, (const float *)L.sq, B, L.head, st);
+  hipLaunchKernelGGL(head_sum_kernel, dim3(1), dim3(256), 0, s, (const float *)L.head, hchunks, B,
+                     L.grad, L.loss, st);
+  hipLaunchKernelGGL(db2_part_kernel, dim3(rchunks), dim3(256), 0, s, th, (const float *)L.h2,
                      (const float *)L.D, n, L.part_b2, st);
   hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, s, (const float *)L.part_b2,
-                     chunks, (size_t)H, H, L.grad + kB2, st);
+                     rchunks, (size_t)H, H, L.grad + kB2, st);
   hipLaunchKernelGGL(bwd_h1_kernel, dim3(blocks, H / BN), dim3(256), 0, s, th,
                      (const float *)L.ctab, feats, (const float *)L.h2, (const float *)L.D,
                      (const uint16_t *)m->w2_bf16, n, L.part1, st);

@@ -259,6 +259,16 @@ class Server:
                 self._finish(r)
                 self.adm.release(r, "done")
 
+    def prime(self, log: Optional[Callable[[str], None]] = None) -> dict:
+        """Plan every shop's first event (its initial instance) through the same
+        batched path, so that the requests that follow are arrival events; the
+        metrics of this phase are returned and then cleared."""
+        m = self.run([(0.0, s.sid) for s in self.shops if s.event == 0], log=log)
+        self.requests = []
+        self.decodes = 0
+        self.ticks = 0
+        return m
+
     def run(self, schedule: Sequence[Tuple[float, int]], time_limit_s: Optional[float] = None,
             idle_sleep_s: float = 1e-4, log: Optional[Callable[[str], None]] = None,
             log_every: int = 100) -> dict:

@@ -320,16 +320,15 @@ def shops(seed: int = 0, n_shops: int = 512, jobs=(20, 200), stages=(3, 10), mac
 
 def shop_arrivals(seed: int, index: int, inst: Instance, n_events: int) -> List[Arrival]:
     """Arrival events of one shop: Poisson times over the shop's LB0 like the
-    paper-shaped recipe, U{max(2, n/10)..max(3, n/5)} new jobs each with fresh
-    unrelated-machine times, the shop's machine powers and due slack U[1.2, 2.0]."""
+    paper-shaped recipe, U{5..10} new jobs each with fresh unrelated-machine
+    times, the shop's machine powers and due slack U[1.2, 2.0]."""
     rng = np.random.default_rng([seed, index])
     g, om, nm = int(inst.n_stages), int(inst.o_max), inst.n_machines
     qsm = np.asarray(inst.power[0]) if inst.n_jobs else np.ones((g, om), np.int32)
     times = _poisson_times(rng, n_events, makespan_lower_bound(inst.proc, qsm, nm, inst.q_max))
-    lo, hi = max(2, inst.n_jobs // 10), max(3, inst.n_jobs // 5)
     out = []
     for t in times:
-        k = int(rng.integers(lo, hi + 1))
+        k = int(rng.integers(5, 11))
         speed = rng.uniform(0.8, 1.5, size=(g, om))
         p_new = _unrelated(rng, k, speed)
         sl = rng.uniform(1.2, 2.0, size=k)
