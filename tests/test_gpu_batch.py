@@ -189,3 +189,35 @@ def test_batch_of_shops_sampled():
     for s in (0, 17, 39):
         want = oracle.ga_run(shops[s], W.SERVING_GA, 11, s, 0, 10, n_threads=8)
         _same(_state(b, s), want, f"shop {s}")
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batch_large_instance_both_schedules(schedule):
+    """large-200x10x4-6 (512 islands x 8x16 = 65536) in a one-slot batch, in the
+    launch shapes its bench times: sampled islands after a migrating generation
+    against the oracle's own run of them."""
+    from oracle_helpers import oracle_islands
+    torch, ffsga = _ffs()
+    wl = W.config3(0)
+    _say("large instance in a batch, schedule", schedule)
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cfg = ffsga.BatchConfig(n_slots=1, max_jobs=wl.initial.n_jobs, max_genes=wl.initial.n_active,
+                            max_stages=wl.initial.n_stages, o_max=wl.initial.o_max,
+                            max_horizon=d.horizon, ga=ffsga.GaConfig.of(wl.ga, lds_slots=8192),
+                            schedule=schedule, blocks=(8 if schedule == 0 else 2) * n_cu,
+                            use_graph=True)
+    b = ffsga.Batch(cfg)
+    b.set(0, d, wl.seed, wl.shop, 0)
+    b.step(10)
+    b.status()
+    islands = [0, 255, 511]
+    want = oracle_islands(wl.initial, wl.ga, wl.seed, wl.shop, 0, islands, 10)
+    got = _state(b, 0)
+    K = wl.ga.rows * wl.ga.cols
+    for I in islands:
+        sl = slice(I * K, (I + 1) * K)
+        assert (got["prio"][sl] == want["prio"][sl]).all(), I
+        assert (got["obj"][sl] == want["obj"][sl]).all(), I
+        assert (got["elite"][I] == want["elite"][I]).all(), I
+        assert got["elite_obj"][I] == want["elite_obj"][I], I

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle_helpers import oracle_islands
 from paper_1903_10741_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -79,56 +80,50 @@ def test_ga_config2_first_event_prefix():
     ga.status()
 
 
-def _chained_check(ga, inst, gacfg, seed, shop, event, islands, ffsga):
-    before = _state(ga)
-    gen = ga.generation + 1
-    ga.step(1)
-    after = _state(ga)
-    sel = np.zeros(gacfg.islands, bool)
-    sel[islands] = True
-    want = oracle.ga_generation(inst, gacfg, seed, shop, event, gen, before, island_sel=sel,
-                                n_threads=8)
-    K = gacfg.rows * gacfg.cols
+def _same_islands(got, want, islands, K, what):
     for I in islands:
         sl = slice(I * K, (I + 1) * K)
-        assert (after["prio"][sl] == want["prio"][sl]).all(), (gen, I)
-        assert (after["obj"][sl] == want["obj"][sl]).all(), (gen, I)
-        assert (after["elite"][I] == want["elite"][I]).all(), (gen, I)
-        assert after["elite_obj"][I] == want["elite_obj"][I], (gen, I)
+        assert (got["prio"][sl] == want["prio"][sl]).all(), (what, I)
+        assert (got["obj"][sl] == want["obj"][sl]).all(), (what, I)
+        assert (got["elite"][I] == want["elite"][I]).all(), (what, I)
+        assert got["elite_obj"][I] == want["elite_obj"][I], (what, I)
 
 
-def test_ga_config2_full_event_chained():
-    """Config 2's whole first event (500 generations): sampled islands are
-    recomputed by the oracle from the GPU's own previous generation, at plain
-    and migrating generations across the run."""
+def test_ga_config2_full_event():
+    """Config 2's whole first event (500 generations) against the oracle's own
+    500-generation run, compared whole at generations 99, 250 and 500."""
     torch, ffsga = _ffs()
     wl = W.config2(0)
-    _say("config 2, 500 generations, chained checks")
+    _say("config 2, 500 generations, whole state at 99, 250, 500")
     d = ffsga.DeviceInstance.from_host(wl.initial)
     ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
-    rng = np.random.default_rng(1)
-    for stop in (9, 99, 249, 449, 499):
-        ga.step(stop - ga.generation)
-        _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0,
-                       sorted(rng.choice(32, 3, replace=False)), ffsga)
+    st = oracle.ga_init(wl.initial, wl.ga, wl.seed, wl.shop, 0, n_threads=8)
+    for k in range(1, 501):
+        st = oracle.ga_generation(wl.initial, wl.ga, wl.seed, wl.shop, 0, k, st, n_threads=8)
+        if k in (99, 250, 500):
+            ga.step(k - ga.generation)
+            _same(_state(ga), st, f"gen {k}")
     assert ga.generation == 500
     ga.status()
 
 
-def test_ga_config3_chained_sample():
-    """Config 3 (512 islands x 8x16 = 65536): chained checks of sampled islands
-    at a plain and a migrating generation."""
+def test_ga_config3_sampled_islands():
+    """Config 3 (512 islands x 8x16 = 65536): sampled islands against the oracle's
+    own run of them (and of what they depend on), at a plain and a migrating
+    generation."""
     torch, ffsga = _ffs()
     wl = W.config3(0)
-    _say("config 3, pop 65536, chained checks")
+    _say("config 3, pop 65536, sampled islands")
     d = ffsga.DeviceInstance.from_host(wl.initial)
     ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
     want0 = oracle.ga_init(wl.initial, W.GaParams(1, 8, 16), wl.seed, wl.shop, 0, n_threads=8)
     got0 = _state(ga)
     assert (got0["prio"][:128] == want0["prio"]).all() and (got0["obj"][:128] == want0["obj"]).all()
-    ga.step(8)
-    _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0, [0, 77, 511], ffsga)   # gen 9
-    _chained_check(ga, wl.initial, wl.ga, wl.seed, wl.shop, 0, [1, 300], ffsga)       # gen 10
+    K = wl.ga.rows * wl.ga.cols
+    for G, islands in ((9, [0, 77, 511]), (10, [1, 300, 511])):   # generation 10 migrates
+        ga.step(G - ga.generation)
+        want = oracle_islands(wl.initial, wl.ga, wl.seed, wl.shop, 0, islands, G)
+        _same_islands(_state(ga), want, islands, K, f"gen {G}")
     ga.status()
 
 

@@ -613,3 +613,21 @@ def test_freeze_boundaries_follow_algorithm1():
     assert nxt.ready[1] == 20 and nxt.ready[2] == 25
     assert nxt.frozen_cmax == 20 and nxt.frozen_tardiness == 0
     assert nxt.machine_free[0][0] == 25 and nxt.machine_free[1][0] == 20
+
+
+def test_island_subset_runs_follow_the_migration_cone():
+    """oracle_islands (the tests' subset runs) equals the whole run on its target
+    islands, across migrating generations."""
+    from oracle_helpers import oracle_islands
+    inst = W.random_instance(31, n_jobs=9, n_stages=2, machines=2)
+    ga = W.GaParams(8, 2, 4, mig_interval=3, mig_k=2)
+    full = oracle.ga_run(inst, ga, 4, 1, 0, 7)
+    K = ga.rows * ga.cols
+    for islands in ([0], [3, 6], [7]):
+        part = oracle_islands(inst, ga, 4, 1, 0, islands, 7)
+        for I in islands:
+            sl = slice(I * K, (I + 1) * K)
+            assert (part["prio"][sl] == full["prio"][sl]).all()
+            assert (part["obj"][sl] == full["obj"][sl]).all()
+            assert (part["elite"][I] == full["elite"][I]).all()
+            assert part["elite_obj"][I] == full["elite_obj"][I]
