@@ -265,9 +265,9 @@ def bench_surrogate(args):
     over the screened GA's time to reach it, and the value is the median.
 
     Per instance (the value): the network is trained on 2.03 M decoder-labelled
-    chromosomes of that instance (the populations of 16 seeded plain-GA runs,
-    generations 0-30), 2 epochs of Adam; data and training time are reported
-    apart. Across instances (reported beside it): one network trained on
+    chromosomes of that instance (the populations of 16 seeded plain-GA runs at
+    generations 0-30, or 0, 10, ..., 300 with --train-snapshots spread), 2 epochs
+    of Adam; data and training time are reported apart. Across instances (reported beside it): one network trained on
     instances of seeds 100-199 (generations 0, 10, 20, 40, 80 of one run each,
     2.05 M chromosomes) and raced on the same unseen instances."""
     import numpy as np
@@ -362,8 +362,9 @@ def bench_surrogate(args):
         model = ffsga.Surrogate(W.surrogate_init(args.seed))
         feats = model.features(d)
         data = []
+        snaps = tuple(range(31)) if args.train_snapshots == "early" else tuple(range(0, 301, 10))
         for rs in range(1000, 1016):
-            prio, obj = populations(d, cfg, rs, tuple(range(31)))
+            prio, obj = populations(d, cfg, rs, snaps)
             data.append((feats, prio, model.targets(obj, pop)))
         torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
@@ -388,7 +389,8 @@ def bench_surrogate(args):
                                  f"instances {args.seed}-{args.seed + args.race_seeds - 1}; value: "
                                  "median over instances of the own-instance network's speedup (0 "
                                  "where the screened run never reaches the target)",
-                     "own_instance": {**own, "training": prep},
+                     "own_instance": {**own, "training": prep,
+                                      "train_snapshots": args.train_snapshots},
                      "cross_instance": {**crs, "train_pairs": cross_pairs, "train_steps": cross_fit[0],
                                         "loss_first": cross_fit[1], "loss_last50": cross_fit[2],
                                         "data_and_train_s": t_cross}})
@@ -415,6 +417,9 @@ def main():
     ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--race-seeds", type=int, default=10)
     ap.add_argument("--train-instances", type=int, default=100)
+    ap.add_argument("--train-snapshots", default="early", choices=["early", "spread"],
+                    help="surrogate: train on generations 0-30 (early) or 0, 10, ..., 300 (spread) "
+                         "of each seeded run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch: the usual tuned configuration (8192 profile slots in 3 classes, "
                          "8 blocks per CU, one wave per child, graph) without tuning")
