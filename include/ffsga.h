@@ -158,6 +158,11 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
  * best of self and four torus neighbours, neighbour-paired single-point
  * crossover with priority correction, swap mutation, decode, elitist
  * replacement, ring migration every mig_interval generations.
+ * A decode that outgrows the on-chip slots is redone off chip by its own
+ * wave when the workspace holds an off-chip profile for every individual
+ * (pop x (horizon + 64) bytes rounded to 256, used up to 1 GiB and counted by
+ * ffs_ga_workspace_size), else by a separate kernel after the generation;
+ * the results are the same either way.
  * Errors: FFS_E_INVAL, FFS_E_DEVICE. */
 int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream);
 

@@ -135,6 +135,11 @@ struct LdsProfile {
   // Add four packed byte increments to the word of slots [x4, x4 + 4), x4 % 4 == 0.
   __device__ void add_word(int x4, uint32_t w) const { atomicAdd((uint32_t *)(p + x4), w); }
   __device__ void order() const { __asm__ volatile("" ::: "memory"); }
+  __device__ int place(int t0, int p, uint32_t thr) const;
+  __device__ void commit(int t, int p, int q) const;
+  __device__ void add_running(int len, int q) const {
+    for (int x = __lane_id(); x < len; x += kWave) add(x, (uint32_t)q);
+  }
 };
 
 // Profile with one byte per slot in global memory (overflow tier). Each
@@ -162,7 +167,69 @@ struct GlobalProfile {
     __hip_atomic_fetch_add((uint32_t *)(p + x4), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __device__ void order() const { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+  __device__ int place(int t0, int p, uint32_t thr) const;
+  __device__ void commit(int t, int p, int q) const;
+  __device__ void add_running(int len, int q) const {
+    for (int x = __lane_id(); x < len; x += kWave) add(x, (uint32_t)q);
+  }
 };
+
+// Push right (Algorithm 2) over a byte profile: the earliest t >= t0 with
+// every slot of [t, t + p) at most thr. The lanes hold the 64 slots
+// [scan, scan + 64); a ballot marks the window's slots that break the peak and
+// t jumps past the last of them, re-testing the same chunk; a clean window
+// part that runs off the chunk moves on to the next 64 slots. Reads past cap
+// land in the 64 zero slots after it.
+template <class Prof>
+__device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint32_t thr) {
+  const int lane = __lane_id(), cap = prof.cap;
+  int t = t0, scan = min(t0, cap);
+  uint32_t v = prof.get(scan + lane);
+  for (;;) {
+    // slots of [t, t + p) in this chunk (one unsigned compare) that break the peak
+    const u64 hit = ballot64((uint32_t)(scan + lane - t) < (uint32_t)p) & ballot64(v > thr);
+    if (hit) {
+      t = scan + (kWave - __clzll(hit));
+      continue;
+    }
+    if (t + p <= scan + kWave || scan + kWave >= cap) break;
+    scan += kWave;
+    v = prof.get(scan + lane);
+  }
+  return t;
+}
+
+// Commit q on [t, t + p) of a byte profile. The lanes cover the word-aligned
+// slots [base, base + 64): each quad of lanes holds one profile word, sums its
+// four byte increments (no carries: every byte stays <= Q_max) and its first
+// lane adds the word, so no two lanes add to one word. Slots past cap (the
+// decode is then redone off chip) are clamped onto the last word, so the zero
+// slots after cap stay zero.
+template <class Prof>
+__device__ __forceinline__ void commit_bytes(const Prof &prof, int t, int p, int q) {
+  const int lane = __lane_id(), cap = prof.cap;
+  const int base = t & ~3;
+  uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
+  c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
+  c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);
+  if ((lane & 3) == 0 && c != 0u) prof.add_word(min(base + lane, cap - 4), c);
+  if (t - base + p > kWave)  // windows longer than the lanes
+    for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
+  prof.order();
+}
+
+__device__ __forceinline__ int LdsProfile::place(int t0, int p, uint32_t thr) const {
+  return place_bytes(*this, t0, p, thr);
+}
+__device__ __forceinline__ void LdsProfile::commit(int t, int p, int q) const {
+  commit_bytes(*this, t, p, q);
+}
+__device__ __forceinline__ int GlobalProfile::place(int t0, int p, uint32_t thr) const {
+  return place_bytes(*this, t0, p, thr);
+}
+__device__ __forceinline__ void GlobalProfile::commit(int t, int p, int q) const {
+  commit_bytes(*this, t, p, q);
+}
 
 enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 
@@ -237,7 +304,7 @@ __device__ __forceinline__ int wave_max32(int v) {
 // once and a ballot marks those that would break the peak; the scalar unit
 // moves the start past the last of them inside the window.
 template <int MAXM, bool PLAN, class Prof>
-__device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64_t *obj_out,
+__device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *obj_out,
                            int64_t *work_out, int32_t *start_out, int32_t *mach_out,
                            int32_t *span_max = nullptr) {
   const int lane = __lane_id();
@@ -272,7 +339,7 @@ __device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64
     const int len = ld_const(I.running, 2 * r) - I.rs;
     const uint32_t q = (uint32_t)ld_const(I.running, 2 * r + 1);
     if (len > prof.cap) return kDecOverflow;
-    for (int x = lane; x < len; x += kWave) prof.add(x, q);
+    prof.add_running(len, (int)q);
   }
   prof.order();
 
@@ -335,44 +402,11 @@ __device__ int decode_core(const DInst &I, const Lds &l, const Prof &prof, int64
       const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)pqv, mb);
       const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
       // Q > Q_max is rejected by the instance checks; even then the unsigned
-      // threshold below only makes every slot pass, so the loop still ends.
+      // threshold below only makes every slot pass, so the push-right still ends.
       const uint32_t thr = (uint32_t)(I.q_max - q);
-      // Push right: the earliest t >= t0 with every slot of [t, t+p) at most
-      // thr. The lanes hold the 64 slots [scan, scan+64); a ballot marks the
-      // window's slots that break the peak and t jumps past the last of them,
-      // re-testing the same chunk; a clean window part that runs off the
-      // chunk moves on to the next 64 slots.
       const int t0 = e - p - rs;
-      int t = t0, scan = min(t0, cap);
-      uint32_t v = prof.get(scan + lane);
-      for (;;) {
-        // slots of [t, t + p) in this chunk (one unsigned compare) that break the peak
-        const u64 hit = ballot64((uint32_t)(scan + lane - t) < (uint32_t)p) & ballot64(v > thr);
-        if (hit) {
-          t = scan + (kWave - __clzll(hit));
-          continue;
-        }
-        if (t + p <= scan + kWave || scan + kWave >= cap) break;
-        scan += kWave;
-        v = prof.get(scan + lane);
-      }
-      // Commit q on [t, t + p). The lanes cover the word-aligned slots
-      // [base, base + 64): each quad of lanes holds one profile word, sums its
-      // four byte increments (no carries: every byte stays <= Q_max) and its
-      // first lane adds the word, so no two lanes add to one word. A window
-      // past the on-chip slots (found once per stage from the machines' end
-      // times) makes this decode be redone off chip; reads stay in the zero
-      // padding and writes are clamped meanwhile.
-      {
-        const int base = t & ~3;
-        uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
-        c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
-        c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);
-        if ((lane & 3) == 0 && c != 0u) prof.add_word(min(base + lane, cap - 4), c);
-        if (t - base + p > kWave)  // windows longer than the lanes
-          for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
-      }
-      prof.order();
+      const int t = prof.place(t0, p, thr);
+      prof.commit(t, p, q);
       const int end = t + p + rs;
       fr = lane == mb ? end : fr;
       endk[k] = PLAN ? end | (mb << 27) : end;
@@ -467,7 +501,7 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
   extern __shared__ __align__(16) uint8_t smem[];
   Lds l = carve_lds(smem, I.n, MAXM);
   const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const GlobalProfile prof{gprof + gstride * blockIdx.x, I.horizon};
+  GlobalProfile prof{gprof + gstride * blockIdx.x, I.horizon};
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     const int i = uni(ovf_list[e]);
     const int32_t *src = prio + (size_t)i * I.n;
@@ -508,6 +542,10 @@ struct GaDev {
   int64_t *stage_obj;    // [islands][mig_k]
   Header *hdr;
   int32_t *ovf_list;
+  // An off-chip profile per individual (redo_stride bytes each) for redoing
+  // its own overflowed decode; null when the overflow kernel does the redo.
+  uint8_t *redo_prof;
+  size_t redo_stride;
   u64 seed, shop;
   int32_t event, rows, cols, islands, mig_k;
   uint32_t pc, pm;
@@ -670,14 +708,24 @@ __device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
   for (int k = lane; k < n; k += kWave) dst[k] = l.gene[k];
 }
 
-// Decode l.gene for slot i and record the outcome: the objective, the work
-// count, or an overflow entry `tag` for the off-chip redo.
+// Decode l.gene for slot i (its genes are also in A.prio_out) and record the
+// outcome: the objective, the work count, or an overflow entry `tag` for the
+// off-chip redo, which the wave does itself when it has a profile of its own.
 template <int MAXM>
 __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
                                   int tag) {
   int64_t work = 0;
-  const int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work,
-                                          nullptr, nullptr);
+  int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
+                                    nullptr);
+  if (st == kDecOverflow && A.redo_prof) {
+    const int32_t *src = A.prio_out + (size_t)i * I.n;
+    for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];  // this lane's own stores
+    __asm__ volatile("" ::: "memory");
+    work = 0;
+    st = decode_core<MAXM, false>(I, l, GlobalProfile{A.redo_prof + A.redo_stride * i, I.horizon},
+                                  A.obj_out + i, &work, nullptr, nullptr);
+    if (st == kDecOverflow) st = kDecInval;  // the horizon bound was wrong: cannot happen
+  }
   if (st == kDecOk) {
     if (__lane_id() == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
     return;
@@ -685,6 +733,51 @@ __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap
   if (__lane_id() == 0) A.obj_out[i] = -1;
   if (st == kDecOverflow) push_overflow(A.hdr, A.ovf_list, tag);
   else flag_error(A.hdr, st);
+}
+
+template <bool MAX>
+__device__ void wave_arg(int64_t &v, int &idx) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int64_t ov = __shfl_xor(v, d, kWave);
+    const int oi = __shfl_xor(idx, d, kWave);
+    const bool take = MAX ? (ov > v || (ov == v && oi < idx)) : (ov < v || (ov == v && oi < idx));
+    if (take) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// Replacement of island I by one wave (same rule as replace_island).
+__device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
+  const int lane = __lane_id(), base = I * K;
+  int64_t bv = LLONG_MAX, wv = LLONG_MIN;
+  int b = INT_MAX, w = INT_MAX;
+  for (int k = lane; k < K; k += kWave) {
+    const int64_t o = A.obj_out[base + k];
+    if (o < bv) {
+      bv = o;
+      b = k;
+    }
+    if (o > wv) {
+      wv = o;
+      w = k;
+    }
+  }
+  wave_arg<false>(bv, b);
+  wave_arg<true>(wv, w);
+  const int64_t old = A.elite_obj[I];
+  if (bv < old) {
+    for (int k = lane; k < n; k += kWave)
+      A.elite[(size_t)I * n + k] = A.prio_out[(size_t)(base + b) * n + k];
+    if (lane == 0) A.elite_obj[I] = bv;
+  }
+  __asm__ volatile("" ::: "memory");
+  // each lane reads back only the elite words it wrote itself
+  for (int k = lane; k < n; k += kWave)
+    A.prio_out[(size_t)(base + w) * n + k] = A.elite[(size_t)I * n + k];
+  if (lane == 0) A.obj_out[base + w] = bv < old ? bv : old;
 }
 
 template <int MAXM>
@@ -986,6 +1079,8 @@ __device__ __forceinline__ GaDev slot_ga(const BatchSlot &S, const BatchArgs &B,
   A.stage_obj = S.stage_obj;
   A.hdr = B.hdr;
   A.ovf_list = nullptr;
+  A.redo_prof = nullptr;
+  A.redo_stride = 0;
   A.seed = S.seed;
   A.shop = S.shop;
   A.event = S.event;
@@ -1023,51 +1118,6 @@ __device__ void decode_slot(const DInst &I, const GaDev &A, int i, int cap, cons
 }
 
 // (value, index) argmin / argmax over one wave, lowest index on ties.
-template <bool MAX>
-__device__ void wave_arg(int64_t &v, int &idx) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const int64_t ov = __shfl_xor(v, d, kWave);
-    const int oi = __shfl_xor(idx, d, kWave);
-    const bool take = MAX ? (ov > v || (ov == v && oi < idx)) : (ov < v || (ov == v && oi < idx));
-    if (take) {
-      v = ov;
-      idx = oi;
-    }
-  }
-}
-
-// Replacement of island I by one wave (same rule as replace_island).
-__device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
-  const int lane = __lane_id(), base = I * K;
-  int64_t bv = LLONG_MAX, wv = LLONG_MIN;
-  int b = INT_MAX, w = INT_MAX;
-  for (int k = lane; k < K; k += kWave) {
-    const int64_t o = A.obj_out[base + k];
-    if (o < bv) {
-      bv = o;
-      b = k;
-    }
-    if (o > wv) {
-      wv = o;
-      w = k;
-    }
-  }
-  wave_arg<false>(bv, b);
-  wave_arg<true>(wv, w);
-  const int64_t old = A.elite_obj[I];
-  if (bv < old) {
-    for (int k = lane; k < n; k += kWave)
-      A.elite[(size_t)I * n + k] = A.prio_out[(size_t)(base + b) * n + k];
-    if (lane == 0) A.elite_obj[I] = bv;
-  }
-  __asm__ volatile("" ::: "memory");
-  // each lane reads back only the elite words it wrote itself
-  for (int k = lane; k < n; k += kWave)
-    A.prio_out[(size_t)(base + w) * n + k] = A.elite[(size_t)I * n + k];
-  if (lane == 0) A.obj_out[base + w] = bv < old ? bv : old;
-}
-
 // One generation of every active slot. ISLAND: an item is an island (its
 // slots in turn, then its replacement); otherwise an item is one child.
 template <int MAXM, bool ISLAND>
@@ -1602,7 +1652,12 @@ struct GaLayout {
   int32_t *ovf_list;
   uint8_t *gprof;
   size_t gstride, total;
+  bool inline_redo;  // one off-chip profile per individual: no overflow kernel
 };
+
+// Off-chip profiles of one per individual are used up to this many bytes;
+// past it the overflow kernel redoes overflowed decodes with kFixBlocks of them.
+constexpr size_t kInlineRedoBytes = (size_t)1 << 30;
 
 GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int cap) {
   GaLayout L{};
@@ -1633,7 +1688,8 @@ GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int
   if (cap < in->horizon) {
     L.gstride = align_up((size_t)in->horizon + 64, 256);
     L.gprof = b + off;
-    off += (size_t)kFixBlocks * L.gstride;
+    L.inline_redo = pop * L.gstride <= kInlineRedoBytes;
+    off += (L.inline_redo ? pop : (size_t)kFixBlocks) * L.gstride;
   }
   L.total = off;
   return L;
@@ -1660,6 +1716,8 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
   A.stage_obj = L.stage_obj;
   A.hdr = L.hdr;
   A.ovf_list = L.ovf_list;
+  A.redo_prof = L.inline_redo ? L.gprof : nullptr;
+  A.redo_stride = L.gstride;
   A.seed = ga->seed;
   A.shop = ga->shop;
   A.event = ga->event;
@@ -1674,7 +1732,7 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
 
 template <int MAXM>
 int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hipStream_t stream) {
-  if (cap >= in->horizon) return FFS_OK;
+  if (cap >= in->horizon || L.inline_redo) return FFS_OK;
   const DInst d = make_dinst(in, L.pq);
   hipError_t e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
                         lds_bytes(in->n_active, 0, MAXM), stream, d, (const int32_t *)L.prio[buf],
