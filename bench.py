@@ -118,7 +118,7 @@ def bench_batch(args):
         rb.set(s, d, args.seed, s, 0)
     rb.stream.synchronize()
     w0 = int(rb.view(0)["work"].item())
-    ffsga.timing_enable(True)
+    ffsga.timing_enable(True, families=[ffsga.TIMING_BATCH])
     rb.step(min(gens, 10))
     gen_ms, launches = ffsga.timing_read(ffsga.TIMING_BATCH)
     ffsga.timing_enable(False)
@@ -468,7 +468,8 @@ def bench_paper(args):
         run_workload(wl, lds_slots=args.lds_slots)
     torch.cuda.synchronize()
 
-    ffsga.timing_enable(True)
+    # events on the generation kernel only: the other launches keep no markers
+    ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION])
     work = 0
     decodes = 0
     best = None

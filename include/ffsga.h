@@ -274,10 +274,12 @@ int ga_batch_destroy(ffs_batch *b);
  * 0 = decode (ffs_decode), 1 = GA generation (breed + decode), 2 = GA
  * replacement, 3 = overflow decode, 4 = batched generation (breed + decode,
  * outside graphs), 5 = screened generation (ffs_surrogate.h: candidate
- * breeding + scoring + decode). enable != 0 starts a fresh count;
+ * breeding + scoring + decode). families: 0 stops timing; otherwise bit f
+ * selects family f (-1: all) and every family's count starts afresh. Only the
+ * selected families get events, so untimed launches carry no event overhead.
  * ffs_timing_read synchronises and returns the summed kernel time and the
- * number of launches since enable. */
-int ffs_timing_enable(int32_t enable);
+ * number of launches since the call. */
+int ffs_timing_enable(int32_t families);
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches);
 
 const char *ffs_strerror(int code);

@@ -1463,6 +1463,7 @@ constexpr int kTimingFamilies = 6;
 struct Timing {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = 0;  // bit f: family f is timed
   std::vector<hipEvent_t> ev[kTimingFamilies];
   size_t used[kTimingFamilies] = {};
   double ms[kTimingFamilies] = {};
@@ -1484,7 +1485,7 @@ template <typename K, typename... Args>
 hipError_t launch(int family, K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t stream,
                   Args... args) {
   if (grid.x == 0) return hipSuccess;
-  if (family >= 0 && g_timing.on) {
+  if (family >= 0 && g_timing.on && ((g_timing.mask >> family) & 1u)) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (g_timing.used[family] == kTimingPairs) {
       drain_family(family, kTimingPairs);
@@ -2471,9 +2472,9 @@ int ga_batch_destroy(ffs_batch *b) {
   return FFS_OK;
 }
 
-int ffs_timing_enable(int32_t enable) {
+int ffs_timing_enable(int32_t families) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
-  if (enable) {
+  if (families) {
     for (int f = 0; f < kTimingFamilies; ++f) {
       if (g_timing.ev[f].empty()) {
         g_timing.ev[f].resize(2 * kTimingPairs);
@@ -2485,7 +2486,8 @@ int ffs_timing_enable(int32_t enable) {
       g_timing.launches[f] = 0;
     }
   }
-  g_timing.on = enable != 0;
+  g_timing.on = families != 0;
+  g_timing.mask = (uint32_t)families;
   return FFS_OK;
 }
 

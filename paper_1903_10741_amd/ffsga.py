@@ -355,8 +355,10 @@ def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.
     return DeviceInstance(nxt, t)
 
 
-def timing_enable(on=True):
-    _check(_lib.ffs_timing_enable(1 if on else 0), "ffs_timing_enable")
+def timing_enable(on=True, families=None):
+    """Time kernel launches with HIP events: every family, or only those listed."""
+    mask = 0 if not on else (-1 if families is None else sum(1 << int(f) for f in families))
+    _check(_lib.ffs_timing_enable(mask), "ffs_timing_enable")
 
 
 def timing_read(family):
