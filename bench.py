@@ -468,8 +468,9 @@ def bench_paper(args):
         run_workload(wl, lds_slots=args.lds_slots)
     torch.cuda.synchronize()
 
-    # events on the generation kernel only: the other launches keep no markers
-    ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION])
+    # events on the generation kernel only, one launch in 8 (spread evenly over
+    # the timed steps): the other launches carry no markers
+    ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION], every=8)
     work = 0
     decodes = 0
     best = None
@@ -531,7 +532,8 @@ def bench_paper(args):
             "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
             "work_per_decode": work_per_decode,
             "avg_launch_us": avg_launch_s * 1e6,
-            "launches": gen_launches,
+            "timed_launches": gen_launches,
+            "timed_every": 8,
             "build_id": ffsga.ffs_build_id(),
         },
     }

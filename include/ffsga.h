@@ -280,6 +280,11 @@ int ga_batch_destroy(ffs_batch *b);
  * ffs_timing_read synchronises and returns the summed kernel time and the
  * number of launches since the call. */
 int ffs_timing_enable(int32_t families);
+
+/* Put events on one launch in `every` (>= 1, default 1) of each timed family,
+ * starting with the first after ffs_timing_enable; ffs_timing_read then counts
+ * the timed launches only. Errors: FFS_E_INVAL. */
+int ffs_timing_every(int32_t every);
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches);
 
 const char *ffs_strerror(int code);

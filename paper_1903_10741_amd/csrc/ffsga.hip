@@ -1464,6 +1464,8 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   uint32_t mask = 0;  // bit f: family f is timed
+  int32_t every = 1;  // one launch in `every` of a timed family gets events
+  int64_t seen[kTimingFamilies] = {};
   std::vector<hipEvent_t> ev[kTimingFamilies];
   size_t used[kTimingFamilies] = {};
   double ms[kTimingFamilies] = {};
@@ -1485,7 +1487,8 @@ template <typename K, typename... Args>
 hipError_t launch(int family, K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t stream,
                   Args... args) {
   if (grid.x == 0) return hipSuccess;
-  if (family >= 0 && g_timing.on && ((g_timing.mask >> family) & 1u)) {
+  if (family >= 0 && g_timing.on && ((g_timing.mask >> family) & 1u) &&
+      g_timing.seen[family]++ % g_timing.every == 0) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (g_timing.used[family] == kTimingPairs) {
       drain_family(family, kTimingPairs);
@@ -2484,10 +2487,18 @@ int ffs_timing_enable(int32_t families) {
       g_timing.used[f] = 0;
       g_timing.ms[f] = 0;
       g_timing.launches[f] = 0;
+      g_timing.seen[f] = 0;
     }
   }
   g_timing.on = families != 0;
   g_timing.mask = (uint32_t)families;
+  return FFS_OK;
+}
+
+int ffs_timing_every(int32_t every) {
+  if (every < 1) return FFS_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  g_timing.every = every;
   return FFS_OK;
 }
 

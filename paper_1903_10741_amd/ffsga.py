@@ -92,13 +92,14 @@ _lib.ffs_reschedule_workspace_size.restype = ctypes.c_size_t
 _lib.reschedule.argtypes = [_P(FfsInstance), _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                             _vp, _vp, _P(FfsInstance), _vp, ctypes.c_size_t, _vp]
 _lib.ffs_timing_enable.argtypes = [ctypes.c_int32]
+_lib.ffs_timing_every.argtypes = [ctypes.c_int32]
 _lib.ffs_timing_read.argtypes = [ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64)]
 _lib.ffs_strerror.argtypes = [ctypes.c_int]
 _lib.ffs_strerror.restype = ctypes.c_char_p
 _lib.ffs_build_id.argtypes = []
 _lib.ffs_build_id.restype = ctypes.c_char_p
 for _f in ("ffs_prepare", "ffs_decode", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
-           "reschedule", "ffs_timing_enable", "ffs_timing_read"):
+           "reschedule", "ffs_timing_enable", "ffs_timing_every", "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -355,9 +356,11 @@ def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.
     return DeviceInstance(nxt, t)
 
 
-def timing_enable(on=True, families=None):
-    """Time kernel launches with HIP events: every family, or only those listed."""
+def timing_enable(on=True, families=None, every=1):
+    """Time kernel launches with HIP events: every family, or only those listed;
+    events on one launch in `every` of each (timing_read counts those)."""
     mask = 0 if not on else (-1 if families is None else sum(1 << int(f) for f in families))
+    _check(_lib.ffs_timing_every(int(every)), "ffs_timing_every")
     _check(_lib.ffs_timing_enable(mask), "ffs_timing_enable")
 
 
@@ -374,7 +377,7 @@ def exported_symbols():
     for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_status",
                  "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
                  "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
-                 "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",
+                 "ffs_timing_every", "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",
                  "ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step",
                  "ga_batch_best", "ga_batch_view", "ga_batch_destroy", "sg_refresh",
                  "sg_features", "sg_table_workspace_size", "sg_score_table", "sg_score",
