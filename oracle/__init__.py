@@ -55,6 +55,7 @@ class _GaParams(ctypes.Structure):
         ("islands", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
         ("pc", ctypes.c_uint32), ("pm", ctypes.c_uint32),
         ("mig_interval", ctypes.c_int32), ("mig_k", ctypes.c_int32),
+        ("encoding", ctypes.c_int32),
     ]
 
 
@@ -101,6 +102,14 @@ def _load():
                                   ctypes.c_int32]
     lib.orc_crossover.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
     lib.orc_crossover.restype = None
+    lib.orc_crossover_xy.argtypes = [ctypes.c_int32, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
+    lib.orc_crossover_xy.restype = None
+    lib.orc_xy_ops.argtypes = [ctypes.POINTER(_Instance)]
+    lib.orc_xy_ops.restype = ctypes.c_int32
+    lib.orc_xy_order.argtypes = [ctypes.POINTER(_Instance), _i32p, _i32p]
+    lib.orc_decode_xy.argtypes = [ctypes.POINTER(_Instance), _i32p, _i64p, _i32p, _i32p, _i64p]
+    lib.orc_decode_xy_pop.argtypes = [ctypes.POINTER(_Instance), _i32p, ctypes.c_int32, _i64p,
+                                      _i64p, ctypes.c_int32]
     lib.orc_correct.argtypes = [ctypes.c_int32, _i32p]
     lib.orc_correct.restype = None
     lib.orc_mutate.argtypes = [ctypes.c_int32, _i32p, ctypes.c_uint64, ctypes.c_uint64]
@@ -109,7 +118,8 @@ def _load():
                                    ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
                                    ctypes.POINTER(_ReschedOut)]
     for f in ("orc_decode", "orc_decode_pop", "orc_decode_ops", "orc_ga_init",
-              "orc_ga_generation", "orc_ga_breed", "orc_ga_finish", "orc_reschedule"):
+              "orc_ga_generation", "orc_ga_breed", "orc_ga_finish", "orc_reschedule",
+              "orc_xy_order", "orc_decode_xy", "orc_decode_xy_pop"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -233,9 +243,71 @@ def decode_ops(inst, ops, start=None, mach=None):
     return int(obj[0]), st, mc
 
 
+def xy_ops(inst):
+    """R: operations not frozen at RS (genes per matrix of an X/Y chromosome)."""
+    return int(_load().orc_xy_ops(_Pinned(inst).ref()))
+
+
+def xy_order(inst, y):
+    """Assignment order Z (Algorithm 1, greedy) from priority genes y[R]: [R, 2] (job, stage)."""
+    lib = _load()
+    p = _Pinned(inst)
+    R = int(lib.orc_xy_ops(p.ref()))
+    yy = _arr(y).reshape(R) if R else np.zeros(1, np.int32)
+    out = np.zeros((max(R, 1), 2), np.int32)
+    _check(lib.orc_xy_order(p.ref(), _ptr(yy), _ptr(out)), "orc_xy_order")
+    return out[:R]
+
+
+def decode_xy(inst, genes, want_schedule=False, want_work=False):
+    """Decode one X/Y chromosome genes[2R]. Returns obj, or (obj, start, mach, work)."""
+    lib = _load()
+    p = _Pinned(inst)
+    R = int(lib.orc_xy_ops(p.ref()))
+    gv = _arr(genes).reshape(-1)
+    if gv.size != 2 * R:
+        raise ValueError("X/Y chromosome length != 2R")
+    if gv.size == 0:
+        gv = np.zeros(2, np.int32)
+    obj = np.zeros(1, np.int64)
+    work = np.zeros(1, np.int64)
+    start = np.full((p.n_jobs, p.g), -1, np.int32) if want_schedule else None
+    mach = np.full((p.n_jobs, p.g), -1, np.int32) if want_schedule else None
+    rc = lib.orc_decode_xy(p.ref(), _ptr(gv), _ptr(obj, _i64p),
+                           _ptr(start) if want_schedule else None,
+                           _ptr(mach) if want_schedule else None, _ptr(work, _i64p))
+    _check(rc, "orc_decode_xy")
+    if want_schedule or want_work:
+        return int(obj[0]), start, mach, int(work[0])
+    return int(obj[0])
+
+
+def decode_xy_pop(inst, genes, n_threads=1, want_work=False):
+    lib = _load()
+    p = _Pinned(inst)
+    R = int(lib.orc_xy_ops(p.ref()))
+    gv = _arr(genes)
+    pop = gv.shape[0]
+    gv = gv.reshape(pop, 2 * R)
+    buf = gv if gv.size else np.zeros(1, np.int32)
+    obj = np.zeros(max(pop, 1), np.int64)
+    work = np.zeros(max(pop, 1), np.int64)
+    rc = lib.orc_decode_xy_pop(p.ref(), _ptr(buf), pop, _ptr(obj, _i64p), _ptr(work, _i64p),
+                               int(n_threads))
+    _check(rc, "orc_decode_xy_pop")
+    if want_work:
+        return obj[:pop], work[:pop]
+    return obj[:pop]
+
+
 def _gp(ga):
     return _GaParams(int(ga.islands), int(ga.rows), int(ga.cols), int(ga.pc), int(ga.pm),
-                     int(ga.mig_interval), int(ga.mig_k))
+                     int(ga.mig_interval), int(ga.mig_k), int(getattr(ga, "encoding", 0)))
+
+
+def _chrom_len(p, gp):
+    """Genes per chromosome: n_active (job priorities) or 2R (X/Y)."""
+    return 2 * int(_load().orc_xy_ops(p.ref())) if gp.encoding == 1 else p.n_active
 
 
 def ga_init(inst, ga, seed, shop, event, n_threads=1):
@@ -244,7 +316,8 @@ def ga_init(inst, ga, seed, shop, event, n_threads=1):
     p = _Pinned(inst)
     gp = _gp(ga)
     pop = gp.islands * gp.rows * gp.cols
-    n = max(p.n_active, 1)
+    L = _chrom_len(p, gp)
+    n = max(L, 1)
     prio = np.zeros((pop, n), np.int32)
     obj = np.zeros(pop, np.int64)
     elite = np.zeros((gp.islands, n), np.int32)
@@ -252,7 +325,7 @@ def ga_init(inst, ga, seed, shop, event, n_threads=1):
     rc = lib.orc_ga_init(p.ref(), ctypes.byref(gp), seed, shop, event, _ptr(prio),
                          _ptr(obj, _i64p), _ptr(elite), _ptr(elite_obj, _i64p), int(n_threads))
     _check(rc, "orc_ga_init")
-    return {"prio": prio[:, :p.n_active].copy(), "obj": obj, "elite": elite[:, :p.n_active].copy(),
+    return {"prio": prio[:, :L].copy(), "obj": obj, "elite": elite[:, :L].copy(),
             "elite_obj": elite_obj}
 
 
@@ -265,7 +338,7 @@ def ga_generation(inst, ga, seed, shop, event, gen, state, island_sel=None, n_th
     p = _Pinned(inst)
     gp = _gp(ga)
     pop = gp.islands * gp.rows * gp.cols
-    n = p.n_active
+    n = _chrom_len(p, gp)
     nn = max(n, 1)
 
     def padded(a, rows):
@@ -302,7 +375,7 @@ def ga_breed(inst, ga, seed, shop, event, gen, variant, state):
     p = _Pinned(inst)
     gp = _gp(ga)
     pop = gp.islands * gp.rows * gp.cols
-    n = p.n_active
+    n = _chrom_len(p, gp)
     nn = max(n, 1)
     prio_in = _arr(state["prio"]).reshape(pop, n) if n else np.zeros((pop, 1), np.int32)
     obj_in = _arr(state["obj"], np.int64).reshape(pop)
@@ -320,7 +393,7 @@ def ga_finish(inst, ga, gen, children, state, n_threads=1):
     p = _Pinned(inst)
     gp = _gp(ga)
     pop = gp.islands * gp.rows * gp.cols
-    n = p.n_active
+    n = _chrom_len(p, gp)
     nn = max(n, 1)
     prio = np.zeros((pop, nn), np.int32)
     prio[:, :n] = _arr(children).reshape(pop, n)
@@ -350,6 +423,17 @@ def ga_best(state):
     """Event result: the best elite, ties to the lowest island."""
     i = int(np.argmin(state["elite_obj"]))
     return state["elite"][i].copy(), int(state["elite_obj"][i])
+
+
+def crossover_xy(a, b, cut):
+    """X/Y crossover of genes[2R] pairs (Fig. 11): both matrices at `cut`, Y corrected."""
+    lib = _load()
+    a = _arr(a)
+    b = _arr(b)
+    ca = np.zeros_like(a)
+    cb = np.zeros_like(b)
+    lib.orc_crossover_xy(int(a.size // 2), _ptr(a), _ptr(b), int(cut), _ptr(ca), _ptr(cb))
+    return ca, cb
 
 
 def crossover(a, b, cut):

@@ -316,6 +316,129 @@ int orc_decode_ops(const orc_instance *in, int32_t n_ops, const int32_t *ops,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The X/Y chromosome (Section 4.3, eqs. (10)-(12), Algorithms 1 and 2)      */
+/* ------------------------------------------------------------------------ */
+int32_t orc_xy_ops(const orc_instance *in) {
+  int32_t R = 0;
+  for (int x = 0; x < in->n_active; ++x) R += in->n_stages - in->first_stage[in->active[x]];
+  return R;
+}
+
+/* Op of gene k: the active jobs in turn, each with its unfrozen stages. */
+static void xy_gene_op(const orc_instance *in, int32_t k, int32_t *job, int32_t *stage) {
+  for (int x = 0; x < in->n_active; ++x) {
+    const int32_t j = in->active[x], len = in->n_stages - in->first_stage[j];
+    if (k < len) {
+      *job = j;
+      *stage = in->first_stage[j] + k;
+      return;
+    }
+    k -= len;
+  }
+  *job = -1;
+  *stage = -1;
+}
+
+/* Gene of op (j, s): the genes of the active jobs before j, then s's place. */
+static int32_t xy_op_gene(const orc_instance *in, int32_t j, int32_t s) {
+  int32_t k = 0;
+  for (int x = 0; x < in->n_active && in->active[x] != j; ++x)
+    k += in->n_stages - in->first_stage[in->active[x]];
+  return k + s - in->first_stage[j];
+}
+
+int orc_xy_order(const orc_instance *in, const int32_t *y, int32_t *order) {
+  const int32_t R = orc_xy_ops(in), n = in->n_active;
+  /* y is a permutation of 1..R, unique priorities (eq. (11)) */
+  uint8_t *seen = (uint8_t *)calloc((size_t)R + 1, 1);
+  int32_t *placed = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!seen || !placed) {
+    free(seen);
+    free(placed);
+    return ORC_E_NOMEM;
+  }
+  for (int k = 0; k < R; ++k) {
+    if (y[k] < 1 || y[k] > R || seen[y[k]]) {
+      free(seen);
+      free(placed);
+      return ORC_E_INVAL;
+    }
+    seen[y[k]] = 1;
+  }
+  /* Algorithm 1, greedy reading: the next op in Z is the one of largest y
+   * among each job's first op not yet ordered (its earlier stages are
+   * ordered or frozen, so the route order of eqs. (4)-(5) holds). */
+  for (int32_t z = 0; z < R; ++z) {
+    int32_t best = -1, best_y = 0, k0 = 0;
+    for (int x = 0; x < n; ++x) {
+      const int32_t j = in->active[x], len = in->n_stages - in->first_stage[j];
+      if (placed[x] < len && y[k0 + placed[x]] > best_y) {
+        best_y = y[k0 + placed[x]];
+        best = x;
+      }
+      k0 += len;
+    }
+    const int32_t j = in->active[best];
+    order[2 * z] = j;
+    order[2 * z + 1] = in->first_stage[j] + placed[best];
+    ++placed[best];
+  }
+  free(seen);
+  free(placed);
+  return ORC_OK;
+}
+
+int orc_decode_xy(const orc_instance *in, const int32_t *genes, int64_t *obj,
+                  int32_t *start, int32_t *mach, int64_t *work) {
+  int rc = check_instance(in);
+  if (rc) return rc;
+  const int32_t R = orc_xy_ops(in);
+  const int32_t *xg = genes, *yg = genes + R;
+  for (int32_t k = 0; k < R; ++k) {  /* x_k is a machine of its op's stage (eq. (10)) */
+    int32_t j, s;
+    xy_gene_op(in, k, &j, &s);
+    if (xg[k] < 0 || xg[k] >= in->n_machines[s]) return ORC_E_INVAL;
+  }
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * 2 * ((size_t)R + 1));
+  if (!order) return ORC_E_NOMEM;
+  if ((rc = orc_xy_order(in, yg, order))) {
+    free(order);
+    return rc;
+  }
+  decoder d;
+  if ((rc = decoder_init(&d, in))) {
+    free(order);
+    return rc;
+  }
+  /* Algorithm 2 in Z order: each op on its target machine x_js. */
+  for (int32_t z = 0; z < R && rc == ORC_OK; ++z) {
+    const int32_t j = order[2 * z], s = order[2 * z + 1];
+    rc = place_op(&d, j, s, xg[xy_op_gene(in, j, s)], start, mach);
+  }
+  if (rc == ORC_OK) {
+    *obj = objective(&d);
+    if (work) *work = d.work;
+  }
+  decoder_free(&d);
+  free(order);
+  return rc;
+}
+
+int orc_decode_xy_pop(const orc_instance *in, const int32_t *genes, int32_t pop,
+                      int64_t *obj, int64_t *work, int32_t n_threads) {
+  int rc = check_instance(in);
+  if (rc) return rc;
+  int bad = 0;
+  const int64_t L = 2 * (int64_t)orc_xy_ops(in);
+#pragma omp parallel for schedule(dynamic, 8) num_threads(n_threads > 0 ? n_threads : 1) reduction(| : bad)
+  for (int32_t i = 0; i < pop; ++i) {
+    int r = orc_decode_xy(in, genes + (int64_t)i * L, &obj[i], NULL, NULL, work ? &work[i] : NULL);
+    if (r) bad |= 1;
+  }
+  return bad ? ORC_E_INVAL : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* GA operators (Section 4.4)                                                */
 /* ------------------------------------------------------------------------ */
 
@@ -329,6 +452,22 @@ void orc_crossover(int32_t n, const int32_t *a, const int32_t *b, int32_t cut,
   }
   orc_correct(n, child_a);
   orc_correct(n, child_b);
+}
+
+/* X/Y crossover (Section 4.4, Fig. 11): the single-point crossover on both
+ * matrices, at the same row-major point (the figure's children are both
+ * matrices cut after their second entry); the Y children are then corrected
+ * like a priority vector. */
+void orc_crossover_xy(int32_t R, const int32_t *a, const int32_t *b, int32_t cut,
+                      int32_t *child_a, int32_t *child_b) {
+  for (int k = 0; k < R; ++k) {
+    child_a[k] = k < cut ? a[k] : b[k];
+    child_b[k] = k < cut ? b[k] : a[k];
+    child_a[R + k] = k < cut ? a[R + k] : b[R + k];
+    child_b[R + k] = k < cut ? b[R + k] : a[R + k];
+  }
+  orc_correct(R, child_a + R);
+  orc_correct(R, child_b + R);
 }
 
 /* Priority correction (Section 4.4, Fig. 11): scanning left to right, the
@@ -366,8 +505,36 @@ void orc_mutate(int32_t n, int32_t *v, uint64_t w1, uint64_t w2) {
 static int check_ga(const orc_instance *in, const orc_ga_params *gp) {
   if (gp->islands < 1 || gp->rows < 1 || gp->cols < 1) return ORC_E_INVAL;
   if (gp->mig_k < 0 || gp->mig_k > gp->rows * gp->cols || gp->mig_interval < 0) return ORC_E_INVAL;
+  if (gp->encoding != 0 && gp->encoding != 1) return ORC_E_INVAL;
   (void)in;
   return ORC_OK;
+}
+
+/* Genes per chromosome: one priority per active job, or X and Y (2R). */
+static int64_t chrom_len(const orc_instance *in, const orc_ga_params *gp) {
+  return gp->encoding == 1 ? 2 * (int64_t)orc_xy_ops(in) : in->n_active;
+}
+
+static int decode_chrom(const orc_instance *in, const orc_ga_params *gp, const int32_t *v,
+                        int64_t *obj) {
+  return gp->encoding == 1 ? orc_decode_xy(in, v, obj, NULL, NULL, NULL)
+                           : orc_decode(in, v, obj, NULL, NULL, NULL);
+}
+
+/* Random unique priorities 1..n (Section 4.3): Fisher-Yates, the d-th draw
+ * taken from word d % 4 of block d / 4 of purpose 0. */
+static void fisher_yates(int32_t *v, int32_t n, uint64_t seed, uint64_t shop, int32_t i,
+                         int32_t event) {
+  for (int k = 0; k < n; ++k) v[k] = k + 1;
+  uint64_t w[4] = {0, 0, 0, 0};
+  for (int32_t pos = n - 1; pos >= 1; --pos) {
+    int32_t d = n - 1 - pos;
+    if (d % 4 == 0) rng_block(seed, shop, (uint64_t)i, 0, (uint64_t)event, 0, (uint64_t)(d / 4), w);
+    int32_t r = (int32_t)draw_below(w[d % 4], (uint32_t)(pos + 1));
+    int32_t tmp = v[pos];
+    v[pos] = v[r];
+    v[r] = tmp;
+  }
 }
 
 int orc_ga_init(const orc_instance *in, const orc_ga_params *gp, uint64_t seed,
@@ -376,24 +543,29 @@ int orc_ga_init(const orc_instance *in, const orc_ga_params *gp, uint64_t seed,
   int rc = check_instance(in);
   if (rc) return rc;
   if ((rc = check_ga(in, gp))) return rc;
-  const int32_t n = in->n_active, K = gp->rows * gp->cols;
-  const int32_t pop = gp->islands * K;
-  /* Random priorities, unique in 1..n (Section 4.3): Fisher-Yates, the d-th
-   * draw taken from word d % 4 of block d / 4. */
+  const int64_t n = chrom_len(in, gp);
+  const int32_t K = gp->rows * gp->cols, pop = gp->islands * K;
   for (int32_t i = 0; i < pop; ++i) {
     int32_t *v = prio + (int64_t)i * n;
-    for (int k = 0; k < n; ++k) v[k] = k + 1;
-    uint64_t w[4] = {0, 0, 0, 0};
-    for (int32_t pos = n - 1; pos >= 1; --pos) {
-      int32_t d = n - 1 - pos;
-      if (d % 4 == 0) rng_block(seed, shop, (uint64_t)i, 0, (uint64_t)event, 0, (uint64_t)(d / 4), w);
-      int32_t r = (int32_t)draw_below(w[d % 4], (uint32_t)(pos + 1));
-      int32_t tmp = v[pos];
-      v[pos] = v[r];
-      v[r] = tmp;
+    if (gp->encoding == 0) {
+      fisher_yates(v, in->n_active, seed, shop, i, event);
+      continue;
     }
+    /* X/Y (Section 4.3): each x a uniform machine of its stage, the k-th draw
+     * from word k % 4 of block k / 4 of purpose 4 (reading: the paper says
+     * only "a random integer"); y unique in 1..R by Fisher-Yates as above. */
+    const int32_t R = (int32_t)(n / 2);
+    uint64_t w[4] = {0, 0, 0, 0};
+    for (int32_t k = 0; k < R; ++k) {
+      int32_t j, st;
+      xy_gene_op(in, k, &j, &st);
+      if (k % 4 == 0) rng_block(seed, shop, (uint64_t)i, 0, (uint64_t)event, 4, (uint64_t)(k / 4), w);
+      v[k] = (int32_t)draw_below(w[k % 4], (uint32_t)in->n_machines[st]);
+    }
+    fisher_yates(v + R, R, seed, shop, i, event);
   }
-  rc = orc_decode_pop(in, prio, pop, obj, NULL, n_threads);
+  rc = gp->encoding == 1 ? orc_decode_xy_pop(in, prio, pop, obj, NULL, n_threads)
+                         : orc_decode_pop(in, prio, pop, obj, NULL, n_threads);
   if (rc) return rc;
   for (int32_t I = 0; I < gp->islands; ++I) {
     int32_t b = I * K;
@@ -446,8 +618,11 @@ int orc_ga_breed(const orc_instance *in, const orc_ga_params *gp,
   if (rc) return rc;
   if ((rc = check_ga(in, gp))) return rc;
   if (gen < 1 || variant < 0) return ORC_E_INVAL;
-  const int32_t n = in->n_active, R = gp->rows, C = gp->cols, K = R * C;
+  const int64_t n = chrom_len(in, gp);
+  const int32_t R = gp->rows, C = gp->cols, K = R * C;
   const int32_t I_n = gp->islands;
+  const int xy = gp->encoding == 1;
+  const int32_t n_genes = xy ? (int32_t)(n / 2) : (int32_t)n;  /* genes per matrix */
   uint8_t *need = needed_islands(gp, gen, island_sel);
 
   for (int32_t I = 0; I < I_n; ++I) {
@@ -460,9 +635,10 @@ int orc_ga_breed(const orc_instance *in, const orc_ga_params *gp,
     /* 2. Crossover of neighbour pairs (Fig. 10 lost). Reading: pairs are
      * horizontal ((r,2c),(r,2c+1)) on odd generations and vertical
      * ((2r,c),(2r+1,c)) on even ones; the lower slot draws the decision and
-     * the cut 1 + floor(hi32 * (n-1) / 2^32). Variant v of the breeding
+     * the cut 1 + floor(hi32 * (n-1) / 2^32) (X/Y: one cut for both matrices,
+     * n = R). Variant v of the breeding
      * (the screened generation's v-th candidate) draws from block v. */
-    if (n >= 2) {
+    if (n_genes >= 2) {
       int32_t *ta = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
       int32_t *tb = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
       const int horizontal = gen % 2 == 1;
@@ -481,20 +657,39 @@ int orc_ga_breed(const orc_instance *in, const orc_ga_params *gp,
         uint64_t w[4];
         rng_block(seed, shop, (uint64_t)a, (uint64_t)gen, (uint64_t)event, 1, (uint64_t)variant, w);
         if ((uint32_t)(w[0] >> 32) < gp->pc) {
-          int32_t cut = 1 + (int32_t)draw_below(w[1], (uint32_t)(n - 1));
+          int32_t cut = 1 + (int32_t)draw_below(w[1], (uint32_t)(n_genes - 1));
           int32_t *pa = prio_out + (int64_t)a * n, *pb = prio_out + (int64_t)b * n;
-          orc_crossover(n, pa, pb, cut, ta, tb);
+          if (xy)
+            orc_crossover_xy(n_genes, pa, pb, cut, ta, tb);
+          else
+            orc_crossover((int32_t)n, pa, pb, cut, ta, tb);
           memcpy(pa, ta, sizeof(int32_t) * (size_t)n);
           memcpy(pb, tb, sizeof(int32_t) * (size_t)n);
         }
       }
       free(ta);
       free(tb);
-      /* 3. Mutation (Fig. 12). */
-      for (int32_t i = I * K; i < (I + 1) * K; ++i) {
-        uint64_t w[4];
-        rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 2, (uint64_t)variant, w);
-        if ((uint32_t)(w[0] >> 32) < gp->pm) orc_mutate(n, prio_out + (int64_t)i * n, w[1], w[2]);
+    }
+    /* 3. Mutation (Fig. 12): the swap of two priorities (n >= 2); with X/Y
+     * every x is also redrawn to another machine of its stage (x + 1 +
+     * draw(o_s - 1)) mod o_s, the k-th draw from word k % 4 of block
+     * variant * ceil(R / 4) + k / 4 of purpose 5 (reading: the paper says
+     * only "random values in the range, apart from the original ones"). */
+    for (int32_t i = I * K; i < (I + 1) * K; ++i) {
+      uint64_t w[4];
+      rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 2, (uint64_t)variant, w);
+      if ((uint32_t)(w[0] >> 32) >= gp->pm) continue;
+      int32_t *v = prio_out + (int64_t)i * n;
+      if (n_genes >= 2) orc_mutate(n_genes, xy ? v + n_genes : v, w[1], w[2]);
+      if (!xy) continue;
+      const uint64_t b0 = (uint64_t)variant * (uint64_t)((n_genes + 3) / 4);
+      uint64_t wx[4] = {0, 0, 0, 0};
+      for (int32_t k = 0; k < n_genes; ++k) {
+        int32_t j, st;
+        xy_gene_op(in, k, &j, &st);
+        if (k % 4 == 0) rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 5, b0 + (uint64_t)(k / 4), wx);
+        const int32_t o = in->n_machines[st];
+        if (o > 1) v[k] = (v[k] + 1 + (int32_t)draw_below(wx[k % 4], (uint32_t)(o - 1))) % o;
       }
     }
   }
@@ -524,7 +719,8 @@ int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
   if (rc) return rc;
   if ((rc = check_ga(in, gp))) return rc;
   if (gen < 1) return ORC_E_INVAL;
-  const int32_t n = in->n_active, K = gp->rows * gp->cols;
+  const int64_t n = chrom_len(in, gp);
+  const int32_t K = gp->rows * gp->cols;
   const int32_t I_n = gp->islands;
   const int migrate = gp->mig_interval > 0 && gp->mig_k > 0 && I_n > 1 && gen % gp->mig_interval == 0;
   uint8_t *need = needed_islands(gp, gen, island_sel);
@@ -534,7 +730,7 @@ int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
 #pragma omp parallel for schedule(dynamic, 8) num_threads(n_threads > 0 ? n_threads : 1) reduction(| : bad)
   for (int32_t i = 0; i < I_n * K; ++i) {
     if (!need[i / K]) continue;
-    if (orc_decode(in, prio_out + (int64_t)i * n, &obj_out[i], NULL, NULL, NULL)) bad |= 1;
+    if (decode_chrom(in, gp, prio_out + (int64_t)i * n, &obj_out[i])) bad |= 1;
   }
   if (bad) {
     free(need);

@@ -77,11 +77,35 @@ int orc_decode_pop(const orc_instance *in, const int32_t *prio, int32_t pop,
 int orc_decode_ops(const orc_instance *in, int32_t n_ops, const int32_t *ops,
                    int64_t *obj, int32_t *start, int32_t *mach);
 
-/* GA parameters. An island is a rows x cols torus; islands are contiguous. */
+/* The paper's own chromosome (Section 4.3, eqs. (10)-(12)): a target-machine
+ * matrix X and a priority matrix Y over the operations. Only unfrozen ops
+ * carry genes (the -1 entries of X and Y have none): R of them, row-major
+ * over the active jobs in active order, stages first_stage..g-1. An X/Y
+ * chromosome is genes[2R] = (x_0..x_{R-1}, y_0..y_{R-1}) with x_k a machine
+ * of the op's stage and y a permutation of 1..R, larger = higher priority. */
+int32_t orc_xy_ops(const orc_instance *in);
+
+/* Assignment order Z (Algorithm 1). Reading: the two rules of Algorithm 1
+ * can contradict each other; Z is built greedily, each step taking, among
+ * the ops whose job's previous stage is already ordered (or frozen), the one
+ * with the largest y. order[R][2] receives (job, stage) in that order. */
+int orc_xy_order(const orc_instance *in, const int32_t *y, int32_t *order);
+
+/* Decode genes[2R]: the ops in Z order, each on its X machine, with the
+ * start rule of orc_decode (Algorithm 2). Outputs as orc_decode; work counts
+ * (S - t0) + 2p per op (no machine choice). */
+int orc_decode_xy(const orc_instance *in, const int32_t *genes, int64_t *obj,
+                  int32_t *start, int32_t *mach, int64_t *work);
+int orc_decode_xy_pop(const orc_instance *in, const int32_t *genes, int32_t pop,
+                      int64_t *obj, int64_t *work, int32_t n_threads);
+
+/* GA parameters. An island is a rows x cols torus; islands are contiguous.
+ * encoding 0: one priority per job (n_active genes); 1: X/Y (2R genes). */
 typedef struct {
   int32_t islands, rows, cols;
   uint32_t pc, pm;             /* crossover / mutation if hi32(draw) < threshold */
   int32_t mig_interval, mig_k; /* ring migration every mig_interval generations */
+  int32_t encoding;
 } orc_ga_params;
 
 /* Population init (generation 0): Fisher-Yates from Philox purpose 0, decode,
@@ -123,6 +147,10 @@ int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
 /* GA building blocks, exposed for the tests. */
 void orc_crossover(int32_t n, const int32_t *a, const int32_t *b, int32_t cut,
                    int32_t *child_a, int32_t *child_b);
+/* X/Y crossover (Section 4.4, Fig. 11): both matrices spliced at gene `cut`,
+ * the Y halves then corrected; genes as in orc_xy_ops (R per matrix). */
+void orc_crossover_xy(int32_t R, const int32_t *a, const int32_t *b, int32_t cut,
+                      int32_t *child_a, int32_t *child_b);
 void orc_correct(int32_t n, int32_t *v);
 void orc_mutate(int32_t n, int32_t *v, uint64_t w1, uint64_t w2);  /* n >= 2 */
 

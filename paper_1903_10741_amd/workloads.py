@@ -76,6 +76,7 @@ class GaParams:
     pm: int = PM_01
     mig_interval: int = 10
     mig_k: int = 1
+    encoding: int = 0   # 0: one priority per job; 1: X/Y matrices over the operations
 
     @property
     def pop(self) -> int:
