@@ -68,6 +68,8 @@ typedef struct {
   const int32_t *active;            /* device [n_active]: unfrozen jobs; gene k <-> active[k] */
   int32_t horizon;                  /* host: slots after RS bounding every completion;
                                        set by ffs_prepare and reschedule */
+  int32_t n_ops;                    /* host: unfrozen operations R = sum over active jobs of
+                                       g - first_stage; set by ffs_prepare and reschedule */
 } ffs_instance;
 
 /* Workspace bytes any ffs_prepare / ffs_status call needs. */
@@ -80,7 +82,7 @@ typedef struct {
  * Errors: FFS_E_INVAL, FFS_E_INFEASIBLE, FFS_E_UNSUPPORTED, FFS_E_DEVICE. */
 int ffs_prepare(ffs_instance *inst, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Device workspace bytes for ffs_decode of `pop` chromosomes. lds_slots: the
+/* Device workspace bytes for ffs_decode or ffs_decode_xy of `pop` chromosomes. lds_slots: the
  * power-profile slots kept on chip per chromosome (0 = library default);
  * decodes that need more fall back to a slower profile in this workspace. */
 size_t ffs_decode_workspace_size(const ffs_instance *inst, int32_t pop, int32_t lds_slots);
@@ -100,6 +102,25 @@ int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64
                int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
                void *workspace, size_t workspace_bytes, void *stream);
 
+/* Decode pop X/Y chromosomes (Section 4.3, eqs. (10)-(12), Algorithms 1-2):
+ * the paper's own encoding, a target machine and a priority per operation.
+ * genes: device [pop][2 * n_ops]. Genes cover the n_ops unfrozen ops only
+ * (the -1 entries of the paper's matrices carry none), row-major over the
+ * active jobs in `active` order, each job's stages first_stage..g-1; the
+ * first n_ops genes are the machines x (0 <= x < o_s of the op's stage), the
+ * last n_ops the priorities y (a permutation of 1..n_ops, larger = higher).
+ * The assignment order Z takes, step by step, the op of largest y among each
+ * job's next unordered op (the greedy reading of Algorithm 1); each op then
+ * starts on machine x at the earliest time after its job's previous stage and
+ * the machine's last op at which the power stays within Q_max (the start rule
+ * of ffs_decode). Outputs, workspace (ffs_decode_workspace_size), lds_slots,
+ * work (per op: slots examined from the first candidate start plus p slots
+ * updated) and errors as ffs_decode; a gene out of range or a y that is not a
+ * permutation sets obj = -1 and makes ffs_status return FFS_E_INVAL. */
+int ffs_decode_xy(const ffs_instance *inst, const int32_t *genes, int32_t pop, int64_t *obj,
+                  int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
 /* Read and clear the device-side error flags of a workspace used by
  * ffs_decode or the GA (any kernel that met a bad input sets them).
  * Synchronises `stream`. Returns FFS_OK, FFS_E_INVAL or FFS_E_INFEASIBLE. */
@@ -115,6 +136,10 @@ typedef struct {
   uint32_t pc, pm;
   int32_t mig_interval, mig_k;
   int32_t lds_slots;                /* on-chip profile slots per decode, 0 = default */
+  int32_t encoding;                 /* 0: one priority per active job (n_genes = n_active);
+                                       1: the paper's X/Y matrices (n_genes = 2 * n_ops, see
+                                       ffs_decode_xy). The batched GA and ga_step_screened
+                                       take encoding 0 only (else FFS_E_UNSUPPORTED). */
 } ffs_ga_params;
 
 /* GA state. Filled by ga_init; the caller owns the struct and the workspace.

@@ -58,7 +58,7 @@ struct Header {
   int32_t pad0;
   int64_t horizon;
   int64_t frozen_tardiness;
-  int32_t frozen_cmax, n_running, n_active, pad1;
+  int32_t frozen_cmax, n_running, n_active, n_ops;  // n_ops: unfrozen ops (ffs_prepare)
   unsigned long long work;  // algorithmic work of every decode of a GA
 };
 static_assert(sizeof(Header) <= kHeaderBytes, "header");
@@ -141,6 +141,14 @@ struct LdsProfile {
     for (int x = __lane_id(); x < len; x += kWave) add(x, (uint32_t)q);
   }
 };
+
+// Slots of an off-chip profile: the horizon bound rounded up to a multiple of
+// 64, like every on-chip cap, so that the commit's clamp onto the last word
+// stays word-aligned and only ever absorbs slots no finished decode reaches.
+// Its region holds offchip_cap + 64 bytes (the zero slots after it).
+__host__ __device__ inline int offchip_cap(int horizon) {
+  return (int)align_up((size_t)horizon, 64);
+}
 
 // Profile with one byte per slot in global memory (overflow tier). Each
 // profile belongs to one single-wave block, so work-group scope orders the
@@ -501,7 +509,7 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
   extern __shared__ __align__(16) uint8_t smem[];
   Lds l = carve_lds(smem, I.n, MAXM);
   const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  GlobalProfile prof{gprof + gstride * blockIdx.x, I.horizon};
+  GlobalProfile prof{gprof + gstride * blockIdx.x, offchip_cap(I.horizon)};
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
     const int i = uni(ovf_list[e]);
     const int32_t *src = prio + (size_t)i * I.n;
@@ -722,8 +730,8 @@ __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap
     for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];  // this lane's own stores
     __asm__ volatile("" ::: "memory");
     work = 0;
-    st = decode_core<MAXM, false>(I, l, GlobalProfile{A.redo_prof + A.redo_stride * i, I.horizon},
-                                  A.obj_out + i, &work, nullptr, nullptr);
+    const GlobalProfile gp{A.redo_prof + A.redo_stride * i, offchip_cap(I.horizon)};
+    st = decode_core<MAXM, false>(I, l, gp, A.obj_out + i, &work, nullptr, nullptr);
     if (st == kDecOverflow) st = kDecInval;  // the horizon bound was wrong: cannot happen
   }
   if (st == kDecOk) {
@@ -797,6 +805,442 @@ __global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) 
   const Lds l = carve_lds(smem, I.n, MAXM);
   init_child(A, I.n, i, l);
   decode_and_record<MAXM>(I, A, i, cap, l, i);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own chromosome: target machines X and operation priorities Y
+// (Section 4.3, eqs. (10)-(12)). Only unfrozen ops carry genes, R of them,
+// row-major over the active jobs (gene k <-> op xyop[k] = x | s << 20 of
+// active job x; job x's genes are [xyg0[x], xyg0[x+1])). A chromosome is
+// 2R ints: the R machines, then the R priorities (a permutation of 1..R,
+// larger = higher).
+// ---------------------------------------------------------------------------
+struct XyTab {
+  const int32_t *op;   // [R]: x | s << 20
+  const int32_t *g0;   // [n + 1]
+  int32_t R;
+};
+
+// LDS of one wave decoding an X/Y chromosome:
+//   gx   [R]      machine genes          gy  [R] priority genes
+//   head [R+1]    per priority value y: k | len << 24 when gene k starts a
+//                 chain of len genes of one job whose running minimum of y is
+//                 y, else 0
+//   zrec [R]      ops in Z order: (x | (s * om + m) << 12, P|Q) for active job x
+//   rdy  [n]      completion of each active job's last placed stage
+//   fm   [g*om]   machine free times
+//   prof [cap+64] power profile bytes
+// head and zrec double as the breeding scratch (correction, Fisher-Yates).
+struct LdsXy {
+  int32_t *gx, *gy;
+  int32_t *head;
+  int2 *zrec;
+  int32_t *rdy, *fm;
+  uint8_t *prof;
+};
+
+__host__ __device__ inline size_t lds_bytes_xy(int n, int R, int g, int om, int cap) {
+  return 3 * align_up((size_t)4 * R + 4, 16) + align_up((size_t)8 * R + 8, 16) +
+         align_up((size_t)4 * n + 4, 16) + align_up((size_t)4 * g * om, 16) +
+         (cap > 0 ? align_up(cap, 16) + kWave : 0);
+}
+
+__device__ __forceinline__ LdsXy carve_lds_xy(uint8_t *smem, int n, int R, int g, int om) {
+  LdsXy l;
+  size_t off = 0;
+  l.gx = (int32_t *)(smem + off);
+  off += align_up((size_t)4 * R + 4, 16);
+  l.gy = (int32_t *)(smem + off);
+  off += align_up((size_t)4 * R + 4, 16);
+  l.head = (int32_t *)(smem + off);
+  off += align_up((size_t)4 * R + 4, 16);
+  l.zrec = (int2 *)(smem + off);
+  off += align_up((size_t)8 * R + 8, 16);
+  l.rdy = (int32_t *)(smem + off);
+  off += align_up((size_t)4 * n + 4, 16);
+  l.fm = (int32_t *)(smem + off);
+  off += align_up((size_t)4 * g * om, 16);
+  l.prof = smem + off;
+  return l;
+}
+
+// Inclusive prefix sum over the 64 lanes (lane order).
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Decode the X/Y chromosome in l.gx / l.gy (Algorithms 1 and 2). Z: the greedy
+// order of Algorithm 1 (the op of largest y among each job's next unordered
+// op) equals the ops sorted by the running minimum of y along each job's
+// stages, descending, ties (same job) by stage: each job splits into chains
+// that start where the running minimum drops, and the chains go out by their
+// head's y, highest first. Each op then goes on its machine x at the
+// earliest power-feasible start after its job's previous stage and the
+// machine's last op, as in decode_core. Every lane calls this; the result is
+// uniform; on kDecOk lane 0 has written *obj_out.
+template <bool PLAN, class Prof>
+__device__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l, Prof &&prof,
+                              int64_t *obj_out, int64_t *work_out, int32_t *start_out,
+                              int32_t *mach_out) {
+  const int lane = __lane_id(), n = I.n, R = T.R;
+  for (int y = lane; y <= R; y += kWave) l.head[y] = 0;
+  __asm__ volatile("" ::: "memory");
+  // x genes name a machine of their stage; y genes are a permutation of 1..R
+  // (each value counted once)
+  int bad = 0;
+  for (int k = lane; k < R; k += kWave) {
+    const int x = l.gx[k], s = ld_const(T.op, k) >> 20;
+    if (x < 0 || x >= ld_const(I.nm, s)) bad = 1;
+    const int y = l.gy[k];
+    if (y < 1 || y > R) bad = 1;
+    else atomicAdd(&l.head[y], 1);
+  }
+  __asm__ volatile("" ::: "memory");
+  for (int y = 1 + lane; y <= R; y += kWave) bad |= l.head[y] != 1;
+  if (ballot64(bad)) return kDecInval;
+  for (int y = lane; y <= R; y += kWave) l.head[y] = 0;
+  __asm__ volatile("" ::: "memory");
+  // chain heads, one job per lane
+  for (int x = lane; x < n; x += kWave) {
+    const int k0 = ld_const(T.g0, x), k1 = ld_const(T.g0, x + 1);
+    int hk = -1, m = INT_MAX;
+    for (int k = k0; k < k1; ++k) {
+      const int y = l.gy[k];
+      if (y < m) {
+        if (hk >= 0) l.head[m] = hk | (k - hk) << 24;
+        hk = k;
+        m = y;
+      }
+    }
+    if (hk >= 0) l.head[m] = hk | (k1 - hk) << 24;
+  }
+  __asm__ volatile("" ::: "memory");
+  // Z: chains by decreasing head value; each op's record
+  int base = 0;
+  for (int y0 = R; y0 >= 1; y0 -= kWave) {
+    const int y = y0 - lane;
+    const int h = y >= 1 ? l.head[y] : 0;
+    const int len = (int)((uint32_t)h >> 24), k = h & 0xFFFFFF;
+    const int incl = wave_scan_incl(len);
+    const int pos = base + incl - len;
+    for (int i = 0; i < len; ++i) {
+      const int kk = k + i, op = ld_const(T.op, kk), x = op & 0xFFFFF, s = op >> 20;
+      const int m = l.gx[kk];
+      const int j = ld_const(I.active, x);
+      const uint32_t pq = ld_const(I.pq, ((size_t)j * I.g + s) * I.omp + m);
+      l.zrec[pos + i] = make_int2(x | (s * I.om + m) << 12, (int)pq);
+    }
+    base += __builtin_amdgcn_readlane(incl, kWave - 1);
+  }
+  for (int x = lane; x < n; x += kWave) l.rdy[x] = ld_const(I.ready, ld_const(I.active, x));
+  for (int x = lane; x < I.g * I.om; x += kWave) l.fm[x] = ld_const(I.mfree, x);
+  prof.clear();
+  prof.order();
+  for (int r = 0; r < I.nr; ++r) {
+    const int len = ld_const(I.running, 2 * r) - I.rs;
+    if (len > prof.cap) return kDecOverflow;
+    prof.add_running(len, ld_const(I.running, 2 * r + 1));
+  }
+  prof.order();
+  __asm__ volatile("" ::: "memory");
+
+  // Ops in Z order. The next op's record, job-ready and machine-free times
+  // are read one op ahead; an op that frees the next op's job or machine
+  // hands its end over directly.
+  const int rs = I.rs, cap = prof.cap;
+  int64_t work = 0;
+  int max_end = rs;
+  int2 rec = R > 0 ? l.zrec[0] : make_int2(0, 0);
+  int rdy_n = l.rdy[uni(rec.x) & 0xFFF], fm_n = l.fm[uni(rec.x) >> 12];
+  for (int z = 0; z < R; ++z) {
+    const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
+    const int est = max(rs, uni(rdy_n)), fr = uni(fm_n);
+    rec = l.zrec[min(z + 1, R - 1)];
+    const int xfn = uni(rec.x), xn = xfn & 0xFFF, fn = xfn >> 12;
+    rdy_n = l.rdy[xn];
+    fm_n = l.fm[fn];
+    const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
+    const uint32_t thr = (uint32_t)(I.q_max - q);
+    const int t0 = max(est, fr) - rs;
+    const int t = prof.place(t0, p, thr);
+    prof.commit(t, p, q);
+    const int end = t + p + rs;
+    l.rdy[x] = end;
+    l.fm[f] = end;
+    if (xn == x) rdy_n = end;
+    if (fn == f) fm_n = end;
+    work += (int64_t)(t - t0) + 2 * p;
+    max_end = max(max_end, end);
+    if (PLAN && lane == 0) {
+      const int j = ld_const(I.active, x), s = f / I.om;
+      start_out[(size_t)j * I.g + s] = t + rs;
+      mach_out[(size_t)j * I.g + s] = f - s * I.om;
+    }
+  }
+  if (max_end - rs > cap) return kDecOverflow;
+  __asm__ volatile("" ::: "memory");
+  int64_t tard = 0;
+  int cmax = 0;
+  for (int x = lane; x < n; x += kWave) {
+    const int c = l.rdy[x];
+    const int late = c - ld_const(I.due, ld_const(I.active, x));
+    tard += late > 0 ? late : 0;
+    cmax = max(cmax, c);
+  }
+  tard = wave_sum64(tard);
+  cmax = max(wave_max32(cmax), I.frozen_cmax);
+  if (lane == 0) {
+    *obj_out = (int64_t)I.wt * (I.frozen_t + tard) + cmax;
+    if (work_out) *work_out = work;
+  }
+  return kDecOk;
+}
+
+// Gene/op table of an instance (one block of 1024 threads): the active jobs'
+// gene offsets by a block prefix sum, then each gene's (x, stage).
+__global__ __launch_bounds__(1024) void xy_table_kernel(const int32_t *first, const int32_t *active,
+                                                        int n, int g, int32_t *op, int32_t *g0) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x, per = (n + 1023) / 1024, x0 = t * per, x1 = min(n, x0 + per);
+  int sum = 0;
+  for (int x = x0; x < x1; ++x) sum += g - first[active[x]];
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int k = part[t] - sum;
+  for (int x = x0; x < x1; ++x) {
+    g0[x] = k;
+    for (int s = first[active[x]]; s < g; ++s) op[k++] = x | s << 20;
+  }
+  if (t == 1023) g0[n] = part[1023];
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(64) void decode_xy_kernel(DInst I, XyTab T, const int32_t *__restrict__ genes,
+                                                       int64_t *obj, int64_t *work, int32_t *start,
+                                                       int32_t *mach, Header *hdr, int32_t *ovf_list,
+                                                       int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int i = blockIdx.x;
+  const LdsXy l = carve_lds_xy(smem, I.n, T.R, I.g, I.om);
+  const int32_t *src = genes + (size_t)i * 2 * T.R;
+  for (int k = __lane_id(); k < T.R; k += kWave) {
+    l.gx[k] = src[k];
+    l.gy[k] = src[T.R + k];
+  }
+  __asm__ volatile("" ::: "memory");
+  const size_t plan = (size_t)i * I.n_jobs * I.g;
+  const LdsProfile prof{l.prof, cap};
+  int64_t *w = work ? work + i : nullptr;
+  const int st = start ? decode_xy_core<true>(I, T, l, prof, obj + i, w, start + plan, mach + plan)
+                       : decode_xy_core<false>(I, T, l, prof, obj + i, w, nullptr, nullptr);
+  if (st == kDecOk) return;
+  if (__lane_id() == 0) obj[i] = -1;
+  if (st == kDecOverflow) push_overflow(hdr, ovf_list, i);
+  else flag_error(hdr, st);
+}
+
+// Redo of overflowed X/Y decodes with a global-memory profile (as overflow_kernel).
+template <int MAXM>
+__global__ __launch_bounds__(64) void overflow_xy_kernel(DInst I, XyTab T, const int32_t *__restrict__ genes,
+                                                         int64_t *obj, int64_t *work, int32_t *start,
+                                                         int32_t *mach, Header *hdr,
+                                                         const int32_t *ovf_list, uint8_t *gprof,
+                                                         size_t gstride) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const LdsXy l = carve_lds_xy(smem, I.n, T.R, I.g, I.om);
+  const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  GlobalProfile prof{gprof + gstride * blockIdx.x, offchip_cap(I.horizon)};
+  for (int e = blockIdx.x; e < count; e += gridDim.x) {
+    const int i = uni(ovf_list[e]);
+    const int32_t *src = genes + (size_t)i * 2 * T.R;
+    for (int k = __lane_id(); k < T.R; k += kWave) {
+      l.gx[k] = src[k];
+      l.gy[k] = src[T.R + k];
+    }
+    __asm__ volatile("" ::: "memory");
+    const size_t plan = (size_t)i * I.n_jobs * I.g;
+    int64_t w = 0;
+    int64_t *wp = work ? work + i : &w;
+    const int st = start ? decode_xy_core<true>(I, T, l, prof, obj + i, wp, start + plan, mach + plan)
+                         : decode_xy_core<false>(I, T, l, prof, obj + i, wp, nullptr, nullptr);
+    if (st == kDecOk && !work && __lane_id() == 0) atomicAdd(&hdr->work, (unsigned long long)w);
+    if (st != kDecOk) {
+      if (__lane_id() == 0) obj[i] = -1;
+      flag_error(hdr, st == kDecOverflow ? kDecInval : st);
+    }
+  }
+  __threadfence();
+  if (__lane_id() == 0) {
+    const int done = atomicAdd(&hdr->ovf_done, 1);
+    if (done == (int)gridDim.x - 1) {
+      __hip_atomic_store(&hdr->ovf_count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&hdr->ovf_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Generation 0 of slot i for an X/Y chromosome: each x a uniform machine of
+// its stage (word k % 4 of block k / 4 of purpose 4), y by Fisher-Yates over
+// 1..R as init_child does (purpose 0); stored to A.prio_out (2R ints).
+__device__ void init_child_xy(const GaDev &A, const DInst &I, const XyTab &T, int i,
+                              const LdsXy &l) {
+  const int lane = __lane_id(), R = T.R;
+  for (int b = lane; b < (R + 3) / 4; b += kWave) {
+    u64 w[4];
+    philox((u64)i, 0ull, (u64)A.event, (4ull << 32) | (u64)b, A.seed, A.shop, w);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * b + u;
+      if (k < R) l.gx[k] = (int)draw_below(w[u], (uint32_t)ld_const(I.nm, ld_const(T.op, k) >> 20));
+    }
+  }
+  uint32_t *hi = (uint32_t *)l.zrec;  // R - 1 high words
+  for (int k = lane; k < R; k += kWave) l.gy[k] = k + 1;
+  for (int b = lane; b < (R - 1 + 3) / 4; b += kWave) {
+    u64 w[4];
+    philox((u64)i, 0ull, (u64)A.event, (u64)b, A.seed, A.shop, w);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * b + u < R - 1) hi[4 * b + u] = (uint32_t)(w[u] >> 32);
+  }
+  __asm__ volatile("" ::: "memory");
+  if (lane == 0) {
+    for (int pos = R - 1; pos >= 1; --pos) {
+      const int r = (int)(((u64)hi[R - 1 - pos] * (u64)(pos + 1)) >> 32);
+      const int t = l.gy[pos];
+      l.gy[pos] = l.gy[r];
+      l.gy[r] = t;
+    }
+  }
+  __asm__ volatile("" ::: "memory");
+  int32_t *dst = A.prio_out + (size_t)i * 2 * R;
+  for (int k = lane; k < R; k += kWave) {
+    dst[k] = l.gx[k];
+    dst[R + k] = l.gy[k];
+  }
+}
+
+// Child of slot i for generation gen, X/Y chromosome (Section 4.4): local
+// selection as breed_child; neighbour-paired single-point crossover cutting
+// both matrices at one point (Fig. 11), Y corrected; mutation (Fig. 12) by a
+// swap of two y and, with it, every x moved to another machine of its stage,
+// (x + 1 + draw(o_s - 1)) mod o_s from word k % 4 of block
+// variant * ceil(R / 4) + k / 4 of purpose 5. Stored to A.prio_out.
+__device__ void breed_child_xy(const GaDev &A, const DInst &I, const XyTab &T, int i, int gen,
+                               const LdsXy &l, int variant = 0) {
+  const int lane = __lane_id(), R = T.R, L = 2 * R;
+  const int K = A.rows * A.cols;
+  const int loc = i % K, r = loc / A.cols, c = loc % A.cols;
+  int lead = -1, partner = -1;
+  if (gen & 1) {
+    if ((c | 1) < A.cols) {
+      lead = i - (c & 1);
+      partner = (c & 1) ? i - 1 : i + 1;
+    }
+  } else if ((r | 1) < A.rows) {
+    lead = i - (r & 1) * A.cols;
+    partner = (r & 1) ? i - A.cols : i + A.cols;
+  }
+  const int32_t *mine = A.prio_in + (size_t)select_winner(A, i) * L;
+  bool cross = false;
+  int cut = R;
+  if (lead >= 0 && R >= 2) {
+    u64 w[4];
+    philox((u64)lead, (u64)gen, (u64)A.event, (1ull << 32) | (u64)variant, A.seed, A.shop, w);
+    cross = (uint32_t)(w[0] >> 32) < A.pc;
+    cut = 1 + (int)draw_below(w[1], (uint32_t)(R - 1));
+  }
+  const int32_t *other = cross ? A.prio_in + (size_t)select_winner(A, partner) * L : mine;
+  for (int k = lane; k < R; k += kWave) {
+    const int32_t *src = k < cut ? mine : other;
+    l.gx[k] = src[k];
+    l.gy[k] = src[R + k];
+  }
+  __asm__ volatile("" ::: "memory");
+  if (cross) correct_lds(l.gy, R, (int32_t *)l.head, (int32_t *)l.zrec);
+  u64 w[4];
+  philox((u64)i, (u64)gen, (u64)A.event, (2ull << 32) | (u64)variant, A.seed, A.shop, w);
+  if ((uint32_t)(w[0] >> 32) < A.pm) {
+    if (R >= 2) {
+      const int x = (int)draw_below(w[1], (uint32_t)R);
+      int y = (int)draw_below(w[2], (uint32_t)(R - 1));
+      y += y >= x;
+      if (lane == 0) {
+        const int gx = l.gy[x];
+        l.gy[x] = l.gy[y];
+        l.gy[y] = gx;
+      }
+    }
+    const u64 b0 = (u64)variant * (u64)((R + 3) / 4);
+    for (int b = lane; b < (R + 3) / 4; b += kWave) {
+      u64 v[4];
+      philox((u64)i, (u64)gen, (u64)A.event, (5ull << 32) | (b0 + (u64)b), A.seed, A.shop, v);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 4 * b + u;
+        if (k >= R) break;
+        const int o = ld_const(I.nm, ld_const(T.op, k) >> 20);
+        if (o > 1) l.gx[k] = (l.gx[k] + 1 + (int)draw_below(v[u], (uint32_t)(o - 1))) % o;
+      }
+    }
+    __asm__ volatile("" ::: "memory");
+  }
+  int32_t *dst = A.prio_out + (size_t)i * L;
+  for (int k = lane; k < R; k += kWave) {
+    dst[k] = l.gx[k];
+    dst[R + k] = l.gy[k];
+  }
+}
+
+// decode_and_record for an X/Y chromosome in l (its genes stay in l.gx/l.gy).
+__device__ void decode_and_record_xy(const DInst &I, const XyTab &T, const GaDev &A, int i,
+                                     int cap, const LdsXy &l) {
+  int64_t work = 0;
+  int st = decode_xy_core<false>(I, T, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
+                                 nullptr);
+  if (st == kDecOverflow && A.redo_prof) {
+    work = 0;
+    const GlobalProfile gp{A.redo_prof + A.redo_stride * i, offchip_cap(I.horizon)};
+    st = decode_xy_core<false>(I, T, l, gp, A.obj_out + i, &work, nullptr, nullptr);
+    if (st == kDecOverflow) st = kDecInval;  // the horizon bound was wrong: cannot happen
+  }
+  if (st == kDecOk) {
+    if (__lane_id() == 0) atomicAdd(&A.hdr->work, (unsigned long long)work);
+    return;
+  }
+  if (__lane_id() == 0) A.obj_out[i] = -1;
+  if (st == kDecOverflow) push_overflow(A.hdr, A.ovf_list, i);
+  else flag_error(A.hdr, st);
+}
+
+__global__ __launch_bounds__(64) void ga_init_xy_kernel(DInst I, XyTab T, GaDev A, int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int i = blockIdx.x;
+  const LdsXy l = carve_lds_xy(smem, I.n, T.R, I.g, I.om);
+  init_child_xy(A, I, T, i, l);
+  decode_and_record_xy(I, T, A, i, cap, l);
+}
+
+__global__ __launch_bounds__(64) void ga_generation_xy_kernel(DInst I, XyTab T, GaDev A, int gen,
+                                                              int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int K = A.rows * A.cols;
+  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const LdsXy l = carve_lds_xy(smem, I.n, T.R, I.g, I.om);
+  breed_child_xy(A, I, T, i, gen, l);
+  decode_and_record_xy(I, T, A, i, cap, l);
 }
 
 // Surrogate score of one chromosome (genes 1..n in `gene`, any address
@@ -1134,7 +1578,7 @@ __global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B, int c
     const int gen = S.gen + 1;
     const GaDev A = slot_ga(S, B, gen);
     const Lds l = carve_lds(smem, S.I.n, MAXM);
-    const GlobalProfile gp{gp_mem, S.I.horizon};
+    const GlobalProfile gp{gp_mem, offchip_cap(S.I.horizon)};
     if (ISLAND) {
       const int isl = item % per_slot;
       for (int k = 0; k < K; ++k) {
@@ -1160,7 +1604,7 @@ __global__ __launch_bounds__(64) void batch_init_kernel(BatchArgs B, int d) {
   A0.prio_out = S.prio[0];
   A0.obj_out = S.obj[0];
   const Lds l = carve_lds(smem, S.I.n, MAXM);
-  const GlobalProfile gp{B.gprof + B.gstride * blockIdx.x, S.I.horizon};
+  const GlobalProfile gp{B.gprof + B.gstride * blockIdx.x, offchip_cap(S.I.horizon)};
   for (int i = blockIdx.x; i < B.pop; i += gridDim.x) {
     init_child(A0, S.I.n, i, l);
     decode_slot<MAXM>(S.I, A0, i, S.cap, l, gp, &B.slots[d].span);
@@ -1273,7 +1717,7 @@ __device__ void block_reduce_i64(int64_t v, int64_t *sh, bool is_max, int64_t &o
 __device__ void prepare_body(const PrepArgs &a, Header *h) {
   __shared__ int64_t sh[1024];
   int err = 0;
-  int64_t base = a.rs, sum = 0;
+  int64_t base = a.rs, sum = 0, ops = 0;
   int unfrozen = 0;
   for (int s = threadIdx.x; s < a.g; s += blockDim.x)
     if (a.nm[s] < 1 || a.nm[s] > a.om) err |= kErrInval;
@@ -1294,6 +1738,7 @@ __device__ void prepare_body(const PrepArgs &a, Header *h) {
       continue;
     }
     base = max(base, (int64_t)a.ready[j]);
+    ops += a.g - f;
     for (int s = f; s < a.g; ++s) {
       const int os = min(max(a.nm[s], 1), a.om);
       int pmax = 0;
@@ -1310,14 +1755,16 @@ __device__ void prepare_body(const PrepArgs &a, Header *h) {
   for (int x = threadIdx.x; x < a.g * a.om; x += blockDim.x)
     if (x % a.om < a.nm[x / a.om]) base = max(base, (int64_t)a.mfree[x]);
   for (int r = threadIdx.x; r < a.nr; r += blockDim.x) base = max(base, (int64_t)a.running[2 * r]);
-  int64_t tot_base, tot_sum, tot_unfrozen;
+  int64_t tot_base, tot_sum, tot_unfrozen, tot_ops;
   block_reduce_i64(base, sh, true, tot_base);
   block_reduce_i64(sum, sh, false, tot_sum);
   block_reduce_i64(unfrozen, sh, false, tot_unfrozen);
+  block_reduce_i64(ops, sh, false, tot_ops);
   if (err) atomicOr(&h->err, err);
   if (threadIdx.x == 0) {
     if (tot_unfrozen != a.n) atomicOr(&h->err, kErrInval);
     h->horizon = tot_base - a.rs + tot_sum + 1;
+    h->n_ops = (int32_t)tot_ops;
   }
 }
 
@@ -1565,15 +2012,10 @@ size_t pq_bytes(const ffs_instance *in) {
   return align_up((size_t)in->n_jobs * in->n_stages * omp_of(in->o_max) * 4 + 64, 256);
 }
 
-size_t overflow_bytes(const ffs_instance *in, int32_t pop, int cap) {
-  if (cap >= in->horizon) return 0;
-  return align_up((size_t)pop * 4, 256) +
-         (size_t)kFixBlocks * align_up((size_t)in->horizon + 64, 256);
-}
-
 struct DecodeLayout {
   Header *hdr;
   uint32_t *pq;
+  int32_t *xyop, *xyg0;  // X/Y gene table (ffs_decode_xy)
   int32_t *ovf_list;
   uint8_t *gprof;
   size_t gstride, total;
@@ -1587,10 +2029,14 @@ DecodeLayout decode_layout(void *ws, const ffs_instance *in, int32_t pop, int ca
   off += kHeaderBytes;
   L.pq = (uint32_t *)(b + off);
   off += pq_bytes(in);
+  L.xyop = (int32_t *)(b + off);
+  off += align_up((size_t)4 * in->n_ops + 4, 256);
+  L.xyg0 = (int32_t *)(b + off);
+  off += align_up((size_t)4 * in->n_active + 4, 256);
   if (cap < in->horizon) {
     L.ovf_list = (int32_t *)(b + off);
     off += align_up((size_t)pop * 4, 256);
-    L.gstride = align_up((size_t)in->horizon + 64, 256);
+    L.gstride = align_up((size_t)offchip_cap(in->horizon) + 64, 256);
     L.gprof = b + off;
     off += (size_t)kFixBlocks * L.gstride;
   }
@@ -1615,6 +2061,28 @@ int run_decode(const ffs_instance *in, const int32_t *prio, int32_t pop, int64_t
   }
   return FFS_OK;
 }
+
+template <int MAXM>
+int run_decode_xy(const ffs_instance *in, const int32_t *genes, int32_t pop, int64_t *obj,
+                  int32_t *start, int32_t *mach, int64_t *work, int cap, const DecodeLayout &L,
+                  hipStream_t stream) {
+  const DInst d = make_dinst(in, L.pq);
+  const XyTab T{L.xyop, L.xyg0, in->n_ops};
+  const size_t shmem = lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap);
+  hipError_t e = launch(0, decode_xy_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, T,
+                        genes, obj, work, start, mach, L.hdr, L.ovf_list, cap);
+  if (e != hipSuccess) return FFS_E_DEVICE;
+  if (cap < in->horizon) {
+    e = launch(3, overflow_xy_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
+               lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, 0), stream, d, T,
+               genes, obj, work, start, mach, L.hdr, (const int32_t *)L.ovf_list, L.gprof,
+               L.gstride);
+    if (e != hipSuccess) return FFS_E_DEVICE;
+  }
+  return FFS_OK;
+}
+
+int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t stream);
 
 int pack(const ffs_instance *in, uint32_t *pq, hipStream_t stream) {
   const int rows = in->n_jobs * in->n_stages;
@@ -1654,10 +2122,16 @@ struct GaLayout {
   int32_t *stage_prio;
   int64_t *stage_obj;
   int32_t *ovf_list;
+  int32_t *xyop, *xyg0;  // X/Y gene table (encoding 1)
   uint8_t *gprof;
   size_t gstride, total;
   bool inline_redo;  // one off-chip profile per individual: no overflow kernel
 };
+
+// Genes per chromosome: one priority per active job, or X and Y (2R).
+int64_t chrom_len(const ffs_instance *in, const ffs_ga_params *p) {
+  return p->encoding == 1 ? 2 * (int64_t)in->n_ops : (int64_t)in->n_active;
+}
 
 // Off-chip profiles of one per individual are used up to this many bytes;
 // past it the overflow kernel redoes overflowed decodes with kFixBlocks of them.
@@ -1666,7 +2140,7 @@ constexpr size_t kInlineRedoBytes = (size_t)1 << 30;
 GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int cap) {
   GaLayout L{};
   uint8_t *b = (uint8_t *)ws;
-  const size_t pop = (size_t)p->islands * p->rows * p->cols, n = (size_t)in->n_active;
+  const size_t pop = (size_t)p->islands * p->rows * p->cols, n = (size_t)chrom_len(in, p);
   const size_t kk = p->mig_k > 0 ? p->mig_k : 1;
   size_t off = 0;
   L.hdr = (Header *)(b + off);
@@ -1689,8 +2163,14 @@ GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int
   off += align_up((size_t)p->islands * kk * 8, 256);
   L.ovf_list = (int32_t *)(b + off);
   off += align_up(pop * 4, 256);
+  if (p->encoding == 1) {
+    L.xyop = (int32_t *)(b + off);
+    off += align_up((size_t)4 * in->n_ops + 4, 256);
+    L.xyg0 = (int32_t *)(b + off);
+    off += align_up((size_t)4 * in->n_active + 4, 256);
+  }
   if (cap < in->horizon) {
-    L.gstride = align_up((size_t)in->horizon + 64, 256);
+    L.gstride = align_up((size_t)offchip_cap(in->horizon) + 64, 256);
     L.gprof = b + off;
     L.inline_redo = pop * L.gstride <= kInlineRedoBytes;
     off += (L.inline_redo ? pop : (size_t)kFixBlocks) * L.gstride;
@@ -1705,6 +2185,7 @@ int check_ga_params(const ffs_ga_params *p) {
   const int64_t K = (int64_t)p->rows * p->cols;
   if (p->mig_k > K) return FFS_E_INVAL;
   if (K > 65536 || K * p->islands > (1 << 26)) return FFS_E_UNSUPPORTED;
+  if (p->encoding != 0 && p->encoding != 1) return FFS_E_INVAL;
   return FFS_OK;
 }
 
@@ -1735,26 +2216,51 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
 }
 
 template <int MAXM>
-int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hipStream_t stream) {
+int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hipStream_t stream,
+                bool xy = false) {
   if (cap >= in->horizon || L.inline_redo) return FFS_OK;
   const DInst d = make_dinst(in, L.pq);
-  hipError_t e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
-                        lds_bytes(in->n_active, 0, MAXM), stream, d, (const int32_t *)L.prio[buf],
-                        L.obj[buf], (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
-                        L.hdr, (const int32_t *)L.ovf_list, L.gprof, L.gstride);
+  hipError_t e;
+  if (xy)
+    e = launch(3, overflow_xy_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
+               lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, 0), stream, d,
+               XyTab{L.xyop, L.xyg0, in->n_ops}, (const int32_t *)L.prio[buf], L.obj[buf],
+               (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, L.hdr,
+               (const int32_t *)L.ovf_list, L.gprof, L.gstride);
+  else
+    e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
+               lds_bytes(in->n_active, 0, MAXM), stream, d, (const int32_t *)L.prio[buf],
+               L.obj[buf], (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, L.hdr,
+               (const int32_t *)L.ovf_list, L.gprof, L.gstride);
   return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
+}
+
+int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t stream) {
+  return launch(-1, xy_table_kernel, dim3(1), dim3(1024), 0, stream, in->first_stage, in->active,
+                in->n_active, in->n_stages, op, g0) == hipSuccess
+             ? FFS_OK
+             : FFS_E_DEVICE;
 }
 
 template <int MAXM>
 int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStream_t stream) {
   const DInst d = make_dinst(in, L.pq);
   GaDev A = make_gadev(ga, L, 1);  // generation 0 is written to buffer 0
-  const int pop = ga->pop, cap = ga->lds_slots, n = in->n_active;
+  const int pop = ga->pop, cap = ga->lds_slots, n = ga->n_genes;
   const int K = ga->params.rows * ga->params.cols;
-  if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap, MAXM), stream, d, A,
-             cap) != hipSuccess)
+  const bool xy = ga->params.encoding == 1;
+  int rc;
+  if (xy) {
+    if ((rc = build_xy_table(in, L.xyop, L.xyg0, stream))) return rc;
+    if (launch(1, ga_init_xy_kernel, dim3(pop), dim3(kWave),
+               lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap), stream, d,
+               XyTab{L.xyop, L.xyg0, in->n_ops}, A, cap) != hipSuccess)
+      return FFS_E_DEVICE;
+  } else if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap, MAXM),
+                    stream, d, A, cap) != hipSuccess) {
     return FFS_E_DEVICE;
-  int rc = ga_overflow<MAXM>(in, L, 0, cap, stream);
+  }
+  rc = ga_overflow<MAXM>(in, L, 0, cap, stream, xy);
   if (rc) return rc;
   if (launch(-1, elite_init_kernel, dim3(ga->params.islands), dim3(256), 0, stream,
              (const int32_t *)L.prio[0], (const int64_t *)L.obj[0], L.elite, L.elite_obj, K,
@@ -1776,9 +2282,12 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
                  const Screen *scr = nullptr) {
   GaLayout L = ga_layout(ga->workspace, in, &ga->params, ga->lds_slots);
   const DInst d = make_dinst(in, L.pq);
-  const int pop = ga->pop, cap = ga->lds_slots, n = in->n_active;
+  const int pop = ga->pop, cap = ga->lds_slots, n = ga->n_genes;
   const int K = ga->params.rows * ga->params.cols;
-  const size_t shmem = lds_bytes(n, cap, MAXM);
+  const bool xy = ga->params.encoding == 1;
+  const XyTab T{L.xyop, L.xyg0, in->n_ops};
+  const size_t shmem = xy ? lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap)
+                          : lds_bytes(in->n_active, cap, MAXM);
   for (int32_t k = 0; k < n_gen; ++k) {
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
@@ -1787,11 +2296,14 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     if (scr)
       e = launch(5, ga_screened_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen, cap,
                  scr->table, scr->theta, scr->variants, scr->scores, scr->choice);
+    else if (xy)
+      e = launch(1, ga_generation_xy_kernel, dim3(pop), dim3(kWave), shmem, stream, d, T, A, gen,
+                 cap);
     else
       e = launch(1, ga_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen,
                  cap);
     if (e != hipSuccess) return FFS_E_DEVICE;
-    int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream);
+    int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream, xy);
     if (rc) return rc;
     if (launch(2, replace_kernel, dim3(ga->params.islands), dim3(256), 0, stream, L.prio[1 - cur],
                L.obj[1 - cur], L.elite, L.elite_obj, K, n) != hipSuccess)
@@ -1829,6 +2341,14 @@ void set_lds_limits() {
   (void)hipFuncSetAttribute((const void *)ga_init_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void *)ga_screened_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)decode_xy_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)overflow_xy_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)ga_init_xy_kernel,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)ga_generation_xy_kernel,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
@@ -1885,7 +2405,7 @@ BatchLayout batch_layout(void *ws, const ffs_batch_params *p) {
   L.slot_stride = so;
   L.slot_base = b + off;
   off += so * p->n_slots;
-  L.gstride = align_up((size_t)p->max_horizon + kWave, 256);
+  L.gstride = align_up((size_t)offchip_cap(p->max_horizon) + kWave, 256);
   L.gprof = b + off;
   off += L.gstride * batch_blocks(p);
   L.total = off;
@@ -1904,6 +2424,7 @@ int check_batch_params(const ffs_batch_params *p) {
     return FFS_E_INVAL;
   int rc = check_ga_params(&p->ga);
   if (rc) return rc;
+  if (p->ga.encoding != 0) return FFS_E_UNSUPPORTED;  // batches run job-priority chromosomes
   if (p->n_slots > FFS_BATCH_MAX_SLOTS || p->o_max > 16 || p->max_genes > kMaxGenes ||
       p->max_stages > kMaxStages || p->max_jobs >= (1 << 20) || p->max_horizon >= kMaxTime)
     return FFS_E_UNSUPPORTED;
@@ -2050,13 +2571,14 @@ int ffs_prepare(ffs_instance *inst, void *workspace, size_t workspace_bytes, voi
   if ((rc = err_code(host.err))) return rc;
   if (host.horizon + inst->rs >= kMaxTime) return FFS_E_UNSUPPORTED;
   inst->horizon = (int32_t)host.horizon;
+  inst->n_ops = host.n_ops;
   return FFS_OK;
 }
 
 size_t ffs_decode_workspace_size(const ffs_instance *inst, int32_t pop, int32_t lds_slots) {
   if (check_host(inst) || inst->horizon < 1 || pop < 0) return 0;
   const int cap = resolve_cap(inst, lds_slots);
-  return kHeaderBytes + pq_bytes(inst) + overflow_bytes(inst, pop, cap);
+  return decode_layout(nullptr, inst, pop, cap).total;
 }
 
 int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
@@ -2090,6 +2612,39 @@ int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64
   }
 }
 
+int ffs_decode_xy(const ffs_instance *inst, const int32_t *genes, int32_t pop, int64_t *obj,
+                  int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+                  void *workspace, size_t workspace_bytes, void *stream) {
+  int rc = check_host(inst);
+  if (rc) return rc;
+  if (inst->horizon < 1 || inst->n_ops < 0 || pop < 0 ||
+      (pop > 0 && (!obj || (!genes && inst->n_ops > 0))) || ((start == nullptr) != (mach == nullptr)))
+    return FFS_E_INVAL;
+  if (pop == 0) return FFS_OK;
+  const int cap = resolve_cap(inst, lds_slots);
+  if (lds_bytes_xy(inst->n_active, inst->n_ops, inst->n_stages, inst->o_max, cap) >
+      (size_t)max_lds_bytes())
+    return FFS_E_UNSUPPORTED;
+  if (!workspace || workspace_bytes < ffs_decode_workspace_size(inst, pop, lds_slots))
+    return FFS_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  DecodeLayout L = decode_layout(workspace, inst, pop, cap);
+  if ((rc = clear_header(L.hdr, s))) return rc;
+  if ((rc = pack(inst, L.pq, s))) return rc;
+  if ((rc = build_xy_table(inst, L.xyop, L.xyg0, s))) return rc;
+  switch (omp_of(inst->o_max)) {
+    case 4:
+      set_lds_limits<4>();
+      return run_decode_xy<4>(inst, genes, pop, obj, start, mach, work, cap, L, s);
+    case 8:
+      set_lds_limits<8>();
+      return run_decode_xy<8>(inst, genes, pop, obj, start, mach, work, cap, L, s);
+    default:
+      set_lds_limits<16>();
+      return run_decode_xy<16>(inst, genes, pop, obj, start, mach, work, cap, L, s);
+  }
+}
+
 int ffs_status(void *workspace, void *stream) {
   if (!workspace) return FFS_E_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
@@ -2117,13 +2672,15 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   if (!ga || inst->horizon < 1) return FFS_E_INVAL;
   if ((rc = check_ga_params(params))) return rc;
   const int cap = resolve_cap(inst, params->lds_slots);
-  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
-    return FFS_E_UNSUPPORTED;
+  const size_t lds = params->encoding == 1
+                         ? lds_bytes_xy(inst->n_active, inst->n_ops, inst->n_stages, inst->o_max, cap)
+                         : lds_bytes(inst->n_active, cap, omp_of(inst->o_max));
+  if (lds > (size_t)max_lds_bytes()) return FFS_E_UNSUPPORTED;
   const size_t need = ffs_ga_workspace_size(inst, params);
   if (!workspace || workspace_bytes < need) return FFS_E_WORKSPACE;
   memset(ga, 0, sizeof(*ga));
   ga->params = *params;
-  ga->n_genes = inst->n_active;
+  ga->n_genes = (int32_t)chrom_len(inst, params);
   ga->pop = params->islands * params->rows * params->cols;
   ga->seed = seed;
   ga->shop = shop;
@@ -2171,7 +2728,7 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
 int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream) {
   int rc = check_host(inst);
   if (rc) return rc;
-  if (!ga || !ga->workspace || n_generations < 0 || inst->n_active != ga->n_genes ||
+  if (!ga || !ga->workspace || n_generations < 0 || chrom_len(inst, &ga->params) != ga->n_genes ||
       inst->n_jobs != ga->n_jobs || inst->horizon != ga->horizon)
     return FFS_E_INVAL;
   if (inst->n_active == 0) {
@@ -2202,6 +2759,7 @@ int ga_step_screened(ffs_ga *ga, const ffs_instance *inst, const ffs_surrogate *
                      int32_t *choice, void *stream) {
   int rc = check_host(inst);
   if (rc) return rc;
+  if (ga && ga->params.encoding != 0) return FFS_E_UNSUPPORTED;
   if (!ga || !ga->workspace || n_generations < 0 || inst->n_active != ga->n_genes ||
       inst->n_jobs != ga->n_jobs || inst->horizon != ga->horizon || !model || !model->theta ||
       !table || variants < 1 || variants > FFS_SG_MAX_VARIANTS ||
@@ -2287,6 +2845,7 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
   next->frozen_cmax = host.frozen_cmax;
   next->n_active = host.n_active;
   next->horizon = (int32_t)host.horizon;
+  next->n_ops = host.n_ops;
   return check_host(next);
 }
 

@@ -44,7 +44,7 @@ class FfsInstance(ctypes.Structure):
         ("n_running", ctypes.c_int32), ("running", _vp),
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
         ("n_active", ctypes.c_int32), ("active", _vp),
-        ("horizon", ctypes.c_int32),
+        ("horizon", ctypes.c_int32), ("n_ops", ctypes.c_int32),
     ]
 
 
@@ -53,7 +53,7 @@ class FfsGaParams(ctypes.Structure):
         ("islands", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
         ("pc", ctypes.c_uint32), ("pm", ctypes.c_uint32),
         ("mig_interval", ctypes.c_int32), ("mig_k", ctypes.c_int32),
-        ("lds_slots", ctypes.c_int32),
+        ("lds_slots", ctypes.c_int32), ("encoding", ctypes.c_int32),
     ]
 
 
@@ -79,6 +79,8 @@ _lib.ffs_decode_workspace_size.argtypes = [_P(FfsInstance), ctypes.c_int32, ctyp
 _lib.ffs_decode_workspace_size.restype = ctypes.c_size_t
 _lib.ffs_decode.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
                             ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.ffs_decode_xy.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                               ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
 _lib.ffs_status.argtypes = [_vp, _vp]
 _lib.ffs_ga_workspace_size.argtypes = [_P(FfsInstance), _P(FfsGaParams)]
 _lib.ffs_ga_workspace_size.restype = ctypes.c_size_t
@@ -98,7 +100,7 @@ _lib.ffs_strerror.argtypes = [ctypes.c_int]
 _lib.ffs_strerror.restype = ctypes.c_char_p
 _lib.ffs_build_id.argtypes = []
 _lib.ffs_build_id.restype = ctypes.c_char_p
-for _f in ("ffs_prepare", "ffs_decode", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
+for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
            "reschedule", "ffs_timing_enable", "ffs_timing_every", "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -162,7 +164,7 @@ class DeviceInstance:
             _dptr(t["release"]), _dptr(t["due"]), int(inst.q_max), int(inst.wt), int(inst.rs),
             _dptr(t["first_stage"]), _dptr(t["ready"]), _dptr(t["machine_free"]),
             int(len(inst.running)), _dptr(t["running"]), int(inst.frozen_tardiness),
-            int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0)
+            int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0, 0)
         d = cls(s, t)
         if prepare:
             d.prepare(workspace)
@@ -175,6 +177,11 @@ class DeviceInstance:
     @property
     def horizon(self):
         return int(self.s.horizon)
+
+    @property
+    def n_ops(self):
+        """Unfrozen operations R (genes per matrix of an X/Y chromosome)."""
+        return int(self.s.n_ops)
 
     def prepare(self, workspace=None):
         ws = workspace if workspace is not None else torch.empty(
@@ -189,7 +196,7 @@ class DeviceInstance:
         out["running"] = out["running"][:s.n_running].reshape(-1, 2)
         out["active"] = out["active"][:s.n_active]
         for k in ("n_jobs", "n_stages", "o_max", "q_max", "wt", "rs", "frozen_tardiness",
-                  "frozen_cmax", "horizon"):
+                  "frozen_cmax", "horizon", "n_ops"):
             out[k] = int(getattr(s, k))
         n = out["n_jobs"]
         for k in ("proc", "power"):
@@ -200,8 +207,10 @@ class DeviceInstance:
 
 
 def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
-               want_schedule: bool = False, want_work: bool = False, workspace=None):
-    """Decode prio [pop, n_active] (int32, cuda). Returns obj (int64 [pop]) or a dict."""
+               want_schedule: bool = False, want_work: bool = False, workspace=None,
+               xy: bool = False):
+    """Decode prio [pop, n_active] (int32, cuda), or with xy=True X/Y chromosomes
+    [pop, 2 * n_ops] (ffs_decode_xy). Returns obj (int64 [pop]) or a dict."""
     s = dinst.s
     dev = dinst.t["proc"].device
     prio = prio.to(device=dev, dtype=torch.int32).contiguous()
@@ -218,9 +227,10 @@ def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
         raise FfsError(FFS_E_INVAL, "ffs_decode_workspace_size")
     ws = workspace if workspace is not None and workspace.numel() >= need else torch.empty(
         need, dtype=torch.uint8, device=dev)
-    _check(_lib.ffs_decode(ctypes.byref(s), _dptr(prio), pop, _dptr(obj), _dptr(start),
-                           _dptr(mach), _dptr(work), int(lds_slots), _dptr(ws), ws.numel(),
-                           _stream()), "ffs_decode")
+    fn = _lib.ffs_decode_xy if xy else _lib.ffs_decode
+    _check(fn(ctypes.byref(s), _dptr(prio), pop, _dptr(obj), _dptr(start), _dptr(mach),
+              _dptr(work), int(lds_slots), _dptr(ws), ws.numel(), _stream()),
+           "ffs_decode_xy" if xy else "ffs_decode")
     _check(_lib.ffs_status(_dptr(ws), _stream()), "ffs_decode (device status)")
     if want_schedule or want_work:
         return {"obj": obj, "start": start, "mach": mach, "work": work}
@@ -237,14 +247,17 @@ class GaConfig:
     mig_interval: int = 10
     mig_k: int = 1
     lds_slots: int = 0
+    encoding: int = 0   # 0: one priority per job; 1: X/Y matrices (2 * n_ops genes)
 
     @classmethod
-    def of(cls, ga, lds_slots=0):
-        return cls(ga.islands, ga.rows, ga.cols, ga.pc, ga.pm, ga.mig_interval, ga.mig_k, lds_slots)
+    def of(cls, ga, lds_slots=0, encoding=None):
+        enc = getattr(ga, "encoding", 0) if encoding is None else encoding
+        return cls(ga.islands, ga.rows, ga.cols, ga.pc, ga.pm, ga.mig_interval, ga.mig_k, lds_slots,
+                   enc)
 
     def c(self):
         return FfsGaParams(self.islands, self.rows, self.cols, self.pc, self.pm, self.mig_interval,
-                           self.mig_k, self.lds_slots)
+                           self.mig_k, self.lds_slots, self.encoding)
 
 
 class GA:
@@ -374,7 +387,8 @@ def timing_read(family):
 def exported_symbols():
     """Names declared in include/ffsga.h that the loaded library exports."""
     names = []
-    for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_status",
+    for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_decode_xy",
+                 "ffs_status",
                  "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
                  "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
                  "ffs_timing_every", "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",

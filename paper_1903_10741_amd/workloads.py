@@ -282,6 +282,21 @@ def random_population(seed: int, pop: int, n: int) -> np.ndarray:
     return np.ascontiguousarray(rng.permuted(base, axis=1), dtype=np.int32)
 
 
+
+def random_xy_population(seed: int, pop: int, inst) -> np.ndarray:
+    """Seeded X/Y chromosomes [pop, 2R] for `inst`: R = unfrozen ops, row-major over
+    the active jobs and their stages from first_stage; a uniform machine of the
+    op's stage, then a uniform permutation of 1..R."""
+    rng = np.random.default_rng(seed)
+    stages = [s for j in inst.active for s in range(int(inst.first_stage[j]), int(inst.n_stages))]
+    o = np.asarray(inst.n_machines)[np.asarray(stages, dtype=np.int64)] if stages else np.zeros(0, int)
+    R = len(stages)
+    out = np.empty((pop, 2 * R), np.int32)
+    for i in range(pop):
+        out[i, :R] = (rng.random(R) * o).astype(np.int32)
+        out[i, R:] = rng.permutation(R) + 1
+    return out
+
 def shop_instance(rng, n_jobs, n_stages, machines, wt=10, percent=55):
     """One shop drawn like the paper-shaped recipe: P = max(1, round(U{5..50} x U[0.8,1.5])),
     Q_sm ~ U{2..15}, peak `percent`, R = 0, D = round(U[1.2,2.0] x P-bar)."""

@@ -1,0 +1,137 @@
+"""GPU X/Y chromosome path (ffs_decode_xy, ga_init/ga_step with encoding 1)
+against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10741_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ffs():
+    import torch
+    from paper_1903_10741_amd import ffsga
+    assert torch.cuda.is_available()
+    return torch, ffsga
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _later_event(wl, seed):
+    """The instance after the first arrival, planned from a random job vector."""
+    inst = wl.initial
+    st, mc = oracle.decode(inst, W.random_population(seed, 1, inst.n_active)[0],
+                           want_schedule=True)[1:3]
+    arr = wl.arrivals[0]
+    return W.Instance.from_fields(oracle.reschedule(inst, st, mc, arr.rs, arr.proc, arr.power,
+                                                    arr.release, arr.due))
+
+
+def _cases():
+    for cfg, seed in ((1, 0), (1, 3), (2, 0), (2, 5)):
+        wl = W.CONFIGS[cfg](seed)
+        yield f"cfg{cfg} s{seed} event 0", wl.initial
+        yield f"cfg{cfg} s{seed} event 1", _later_event(wl, seed)
+
+
+def test_decode_xy_matches_oracle():
+    torch, ffsga = _ffs()
+    for name, inst in _cases():
+        d = ffsga.DeviceInstance.from_host(inst)
+        assert d.n_ops == oracle.xy_ops(inst)
+        genes = W.random_xy_population(7, 150, inst)
+        for lds in (0, 64):
+            _say("decode_xy", name, "lds_slots", lds)
+            got = ffsga.ffs_decode(d, torch.from_numpy(genes).cuda(), lds_slots=lds,
+                                   want_schedule=True, want_work=True, xy=True)
+            obj, work = oracle.decode_xy_pop(inst, genes, n_threads=8, want_work=True)
+            assert (got["obj"].cpu().numpy() == obj).all()
+            assert (got["work"].cpu().numpy() == work).all()
+            start, mach = got["start"].cpu().numpy(), got["mach"].cpu().numpy()
+            for i in (0, 77, 149):
+                o, st, mc, _ = oracle.decode_xy(inst, genes[i], want_schedule=True)
+                assert (start[i] == st).all() and (mach[i] == mc).all()
+
+
+def test_decode_xy_table4_example():
+    """The printed X(k) and Y(k) of Section 4.3 give Fig. 8's makespan on the GPU."""
+    torch, ffsga = _ffs()
+    from tests.test_oracle_xy import _example_rescheduled, _genes_of, _printed_y
+    e, inst = _example_rescheduled()
+    genes = np.array([_genes_of(inst, e["X"]) + _genes_of(inst, _printed_y())], np.int32)
+    d = ffsga.DeviceInstance.from_host(inst)
+    obj = ffsga.ffs_decode(d, torch.from_numpy(genes).cuda(), xy=True)
+    assert int(obj[0]) == oracle.decode_xy(inst, genes[0]) == 2042
+
+
+def test_decode_xy_rejects_bad_genes():
+    torch, ffsga = _ffs()
+    wl = W.config1(1)
+    inst = wl.initial
+    genes = W.random_xy_population(2, 4, inst)
+    R = genes.shape[1] // 2
+    genes[1, 0] = 5                  # machine out of range
+    genes[2, R] = genes[2, R + 1]    # duplicate priority
+    d = ffsga.DeviceInstance.from_host(inst)
+    with pytest.raises(ffsga.FfsError):
+        ffsga.ffs_decode(d, torch.from_numpy(genes).cuda(), xy=True)
+
+
+def _state(ga):
+    v = ga.view()
+    return {k: t.cpu().numpy() for k, t in v.items() if k != "work"}
+
+
+def _same(a, b, what):
+    for k in ("prio", "obj", "elite", "elite_obj"):
+        assert (np.asarray(a[k]) == np.asarray(b[k])).all(), (what, k)
+
+
+def test_xy_ga_config1_every_generation():
+    torch, ffsga = _ffs()
+    wl = W.config1(0)
+    gp = W.GaParams(wl.ga.islands, wl.ga.rows, wl.ga.cols, wl.ga.pc, wl.ga.pm,
+                    wl.ga.mig_interval, wl.ga.mig_k, encoding=1)
+    _say("X/Y GA config 1, 50 generations, every generation")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(gp), wl.seed, wl.shop, 0)
+    st = oracle.ga_init(wl.initial, gp, wl.seed, wl.shop, 0)
+    _same(_state(ga), st, "init")
+    for k in range(1, wl.generations + 1):
+        ga.step(1)
+        st = oracle.ga_generation(wl.initial, gp, wl.seed, wl.shop, 0, k, st)
+        _same(_state(ga), st, f"gen {k}")
+    ga.status()
+
+
+def test_xy_ga_config2_and_later_event():
+    torch, ffsga = _ffs()
+    wl = W.config2(0)
+    gp = W.GaParams(4, 8, 16, wl.ga.pc, wl.ga.pm, 10, 2, encoding=1)
+    for name, inst in (("event 0", wl.initial), ("event 1", _later_event(wl, 0))):
+        _say("X/Y GA config 2 shape 4x8x16", name, "30 generations")
+        d = ffsga.DeviceInstance.from_host(inst)
+        ga = ffsga.GA(d, ffsga.GaConfig.of(gp), 3, 1, 1)
+        ga.step(30)
+        ga.status()
+        st = oracle.ga_run(inst, gp, 3, 1, 1, 30, n_threads=8)
+        _same(_state(ga), st, name)
+
+
+def test_xy_ga_overflow_tier_and_determinism():
+    torch, ffsga = _ffs()
+    wl = W.config1(3)
+    gp = W.GaParams(2, 4, 4, mig_interval=3, mig_k=1, encoding=1)
+    _say("X/Y GA lds_slots = 64")
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    runs = []
+    for _ in range(2):
+        ga = ffsga.GA(d, ffsga.GaConfig.of(gp, lds_slots=64), 5, 2, 0)
+        ga.step(10)
+        ga.status()
+        runs.append(_state(ga))
+    _same(runs[0], runs[1], "determinism")
+    _same(runs[0], oracle.ga_run(wl.initial, gp, 5, 2, 0, 10), "overflow tier")
