@@ -407,6 +407,9 @@ def main():
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "batch", "serve", "surrogate", "large"])
     ap.add_argument("--lds-slots", type=int, default=0)
+    ap.add_argument("--encoding", default="job", choices=["job", "xy"],
+                    help="paper workload: one priority per job (default) or the paper's X/Y "
+                         "machine and priority matrices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--generations", type=int, default=None,
@@ -457,6 +460,10 @@ def bench_paper(args):
     wl = W.config2(args.seed)
     if args.generations is not None:
         wl.generations = args.generations
+    xy = args.encoding == "xy"
+    if xy:
+        import dataclasses
+        wl.ga = dataclasses.replace(wl.ga, encoding=1)
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -492,7 +499,8 @@ def bench_paper(args):
     value = decodes / elapsed
     traffic = None
     valu_issue = None
-    tpath = os.path.join(ROOT, "profiles", "ga_generation_kernel_paper-50x5x3.traffic.json")
+    kname = "ga_generation_xy_kernel" if xy else "ga_generation_kernel"
+    tpath = os.path.join(ROOT, "profiles", f"{kname}_paper-50x5x3.traffic.json")
     if os.path.exists(tpath):
         t = json.load(open(tpath))
         if t.get("build_id") == ffsga.ffs_build_id():  # counters of this very build only
@@ -516,14 +524,16 @@ def bench_paper(args):
         "data": "synthetic (seeded generator, paper-shaped)",
         "config": {
             "workload": "paper-shaped plain GA: 50 jobs, 5 stages, 3 unrelated machines, "
-                        "5 arrival events, 32 islands x 8x16 = 4096, 500 generations/event",
+                        "5 arrival events, 32 islands x 8x16 = 4096, 500 generations/event" +
+                        (", X/Y chromosome (machine and priority per operation)" if xy else ""),
+            "encoding": "xy" if xy else "job priority vector",
             "decodes_per_step": decodes // args.steps,
             "events": 1 + len(wl.arrivals),
             "best_obj_per_event": best,
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "ga_generation_kernel (selection, crossover, mutation, decode)",
+            "kernel": f"{kname} (selection, crossover, mutation, decode)",
             "achieved": achieved,
             "peak": VALU_INT32_PEAK_TOPS,
             "unit": "TOP/s int32",

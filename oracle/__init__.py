@@ -517,7 +517,8 @@ def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, ev
     for e in range(n_events):
         st = ga_run(inst, ga, seed, shop, e, generations, n_threads)
         prio, obj = ga_best(st)
-        obj2, s, m, _ = decode(inst, prio, want_schedule=True)
+        dec = decode_xy if getattr(ga, "encoding", 0) == 1 else decode
+        obj2, s, m, _ = dec(inst, prio, want_schedule=True)
         assert obj2 == obj
         for j in np.asarray(inst.active):
             f = int(np.asarray(inst.first_stage)[j])

@@ -54,7 +54,8 @@ def run_workload(wl, device="cuda", generations=None, lds_slots=0, keep_instance
         ga.step(gens)
         prio, obj = ga.best()
         n = int(dinst.s.n_jobs)
-        sched = ffsga.ffs_decode(dinst, prio.view(1, -1), lds_slots=lds_slots, want_schedule=True)
+        sched = ffsga.ffs_decode(dinst, prio.view(1, -1), lds_slots=lds_slots, want_schedule=True,
+                                 xy=cfg.encoding == 1)
         # decoded ops of the best plan overwrite their entries; frozen ones stay
         dec = sched["start"][0] >= 0
         plan_s[:n][dec] = sched["start"][0][dec]

@@ -135,3 +135,24 @@ def test_xy_ga_overflow_tier_and_determinism():
         runs.append(_state(ga))
     _same(runs[0], runs[1], "determinism")
     _same(runs[0], oracle.ga_run(wl.initial, gp, 5, 2, 0, 10), "overflow tier")
+
+
+@pytest.mark.parametrize("cfg,gens", [(1, 50), (2, 10)])
+def test_xy_event_loop_matches_oracle(cfg, gens):
+    """Every event with X/Y chromosomes: GA, executed plan, freeze, reschedule."""
+    torch, ffsga = _ffs()
+    import dataclasses
+    from paper_1903_10741_amd.run import run_workload
+    wl = W.CONFIGS[cfg](0)
+    wl.ga = dataclasses.replace(wl.ga, encoding=1)
+    _say("X/Y event loop config", cfg, "generations", gens)
+    got = run_workload(wl, generations=gens, keep_instances=True)
+    want = oracle.run_events(wl.initial, wl.arrivals, wl.ga, gens, wl.seed, wl.shop, n_threads=8)
+    assert len(got.events) == len(want) == 1 + len(wl.arrivals)
+    for e, (ge, we) in enumerate(zip(got.events, want)):
+        assert ge.best_obj == we["best_obj"], e
+        assert (ge.best_prio.cpu().numpy() == we["best_prio"]).all(), e
+        assert ge.instance.n_ops == oracle.xy_ops(we["instance"]), e
+    n = got.plan_start.shape[0]
+    assert (got.plan_start.cpu().numpy() == want[-1]["plan_start"][:n]).all()
+    assert (got.plan_mach.cpu().numpy() == want[-1]["plan_mach"][:n]).all()
