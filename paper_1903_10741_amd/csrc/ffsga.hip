@@ -822,14 +822,15 @@ struct XyTab {
 };
 
 // LDS of one wave decoding an X/Y chromosome:
-//   gx   [R]      machine genes          gy  [R] priority genes
-//   head [R+1]    per priority value y: k | len << 24 when gene k starts a
-//                 chain of len genes of one job whose running minimum of y is
-//                 y, else 0
+//   gx   [R]      machine genes
 //   zrec [R]      ops in Z order: (x | (s * om + m) << 12, P|Q) for active job x
 //   rdy  [n]      completion of each active job's last placed stage
 //   fm   [g*om]   machine free times
-//   prof [cap+64] power profile bytes
+//   then one region used twice: until Z is built, the priority genes gy [R]
+//   and head [R+1] (per priority value y: k | len << 24 when gene k starts a
+//   chain of len genes of one job whose running minimum of y is y, else 0);
+//   from then on the power profile prof [cap+64]. A decode redone off chip
+//   therefore reloads its genes.
 // head and zrec double as the breeding scratch (correction, Fisher-Yates).
 struct LdsXy {
   int32_t *gx, *gy;
@@ -840,9 +841,11 @@ struct LdsXy {
 };
 
 __host__ __device__ inline size_t lds_bytes_xy(int n, int R, int g, int om, int cap) {
-  return 3 * align_up((size_t)4 * R + 4, 16) + align_up((size_t)8 * R + 8, 16) +
+  const size_t genes = 2 * align_up((size_t)4 * R + 4, 16);
+  const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0;
+  return align_up((size_t)4 * R + 4, 16) + align_up((size_t)8 * R + 8, 16) +
          align_up((size_t)4 * n + 4, 16) + align_up((size_t)4 * g * om, 16) +
-         (cap > 0 ? align_up(cap, 16) + kWave : 0);
+         (genes > prof ? genes : prof);
 }
 
 __device__ __forceinline__ LdsXy carve_lds_xy(uint8_t *smem, int n, int R, int g, int om) {
@@ -850,16 +853,14 @@ __device__ __forceinline__ LdsXy carve_lds_xy(uint8_t *smem, int n, int R, int g
   size_t off = 0;
   l.gx = (int32_t *)(smem + off);
   off += align_up((size_t)4 * R + 4, 16);
-  l.gy = (int32_t *)(smem + off);
-  off += align_up((size_t)4 * R + 4, 16);
-  l.head = (int32_t *)(smem + off);
-  off += align_up((size_t)4 * R + 4, 16);
   l.zrec = (int2 *)(smem + off);
   off += align_up((size_t)8 * R + 8, 16);
   l.rdy = (int32_t *)(smem + off);
   off += align_up((size_t)4 * n + 4, 16);
   l.fm = (int32_t *)(smem + off);
   off += align_up((size_t)4 * g * om, 16);
+  l.gy = (int32_t *)(smem + off);
+  l.head = (int32_t *)(smem + off + align_up((size_t)4 * R + 4, 16));
   l.prof = smem + off;
   return l;
 }
@@ -1204,13 +1205,20 @@ __device__ void breed_child_xy(const GaDev &A, const DInst &I, const XyTab &T, i
   }
 }
 
-// decode_and_record for an X/Y chromosome in l (its genes stay in l.gx/l.gy).
+// decode_and_record for an X/Y chromosome in l (also in A.prio_out, from where
+// an off-chip redo reloads it: the on-chip profile overwrote the priorities).
 __device__ void decode_and_record_xy(const DInst &I, const XyTab &T, const GaDev &A, int i,
                                      int cap, const LdsXy &l) {
   int64_t work = 0;
   int st = decode_xy_core<false>(I, T, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
                                  nullptr);
   if (st == kDecOverflow && A.redo_prof) {
+    const int32_t *src = A.prio_out + (size_t)i * 2 * T.R;
+    for (int k = __lane_id(); k < T.R; k += kWave) {  // this lane's own stores
+      l.gx[k] = src[k];
+      l.gy[k] = src[T.R + k];
+    }
+    __asm__ volatile("" ::: "memory");
     work = 0;
     const GlobalProfile gp{A.redo_prof + A.redo_stride * i, offchip_cap(I.horizon)};
     st = decode_xy_core<false>(I, T, l, gp, A.obj_out + i, &work, nullptr, nullptr);
