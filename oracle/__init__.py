@@ -47,7 +47,12 @@ class _Instance(ctypes.Structure):
         ("n_running", ctypes.c_int32), ("running", _i32p),
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
         ("n_active", ctypes.c_int32), ("active", _i32p),
+        ("decode_rules", ctypes.c_int32),
     ]
+
+
+RULE_FIFO = 1        # decode variant: each stage in order of the previous stage's completion
+RULE_POWER_ECT = 2   # decode variant: machine of earliest completion after the power push-right
 
 
 class _GaParams(ctypes.Structure):
@@ -158,7 +163,8 @@ class _Pinned:
             _ptr(k["release"]), _ptr(k["due"]), int(inst.q_max), int(inst.wt), int(inst.rs),
             _ptr(k["first_stage"]), _ptr(k["ready"]), _ptr(k["machine_free"]),
             int(len(inst.running)), _ptr(k["running"]), int(inst.frozen_tardiness),
-            int(inst.frozen_cmax), int(len(inst.active)), _ptr(k["active"]))
+            int(inst.frozen_cmax), int(len(inst.active)), _ptr(k["active"]),
+            int(getattr(inst, "decode_rules", 0)))
         self.n_active = int(len(inst.active))
         self.n_jobs = n
         self.g = g
@@ -533,6 +539,7 @@ def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, ev
             plan_s = np.vstack([plan_s, np.full((k, g), -1, np.int32)])
             plan_m = np.vstack([plan_m, np.full((k, g), -1, np.int32)])
             inst = _Fields(nxt)
+            inst.decode_rules = int(getattr(initial, "decode_rules", 0))
     return out
 
 

@@ -170,14 +170,30 @@ static int decoder_init(decoder *d, const orc_instance *in) {
   return ORC_OK;
 }
 
-/* Place op (j, s). machine < 0: the machine with the earliest completion time
+/* Push right (Algorithm 2, eqs. (7)-(9)): the earliest t >= t0 such that the
+ * power over [t, t+p) plus q stays within Q_max; a window that breaks the
+ * limit at tau cannot start at or before tau, so the search jumps past its
+ * last breaking slot. */
+static int32_t push_right(const decoder *d, int32_t t0, int32_t p, int32_t q) {
+  const orc_instance *in = d->in;
+  int32_t t = t0;
+  for (;;) {
+    int64_t last_bad = -1;
+    for (int64_t tau = t; tau < (int64_t)t + p; ++tau)
+      if (d->profile[tau - in->rs] + q > in->q_max) last_bad = tau;
+    if (last_bad < 0) return t;
+    t = (int32_t)(last_bad + 1);
+  }
+}
+
+/* Place op (j, s). machine -1: the machine with the earliest completion time
  * max(est, free) + P, ties to the lowest index (reading: machine first, then
- * time, as X(k) is fixed before Algorithm 2 runs). The start is the earliest
- * t >= max(RS, previous stage end or release, machine free) such that the
- * power over [t, t+p) plus q stays within Q_max (eqs. (7)-(9), half-open per
- * eq. (9)); a window that breaks the limit at tau cannot start at or before
- * tau, so the search jumps past its last breaking slot. Machines are
- * append-only: an op goes after every op placed on that machine before it. */
+ * time, as X(k) is fixed before Algorithm 2 runs); -2: the machine of earliest
+ * completion after its push-right (ORC_RULE_POWER_ECT). The start is the
+ * earliest t >= max(RS, previous stage end or release, machine free) such that
+ * the power over [t, t+p) plus q stays within Q_max (eqs. (7)-(9), half-open
+ * per eq. (9)). Machines are append-only: an op goes after every op placed on
+ * that machine before it. */
 static int place_op(decoder *d, int32_t j, int32_t s, int32_t machine,
                     int32_t *start_out, int32_t *mach_out) {
   const orc_instance *in = d->in;
@@ -188,7 +204,7 @@ static int place_op(decoder *d, int32_t j, int32_t s, int32_t machine,
   const int32_t est = MAX32(in->rs, d->done_at[j]);  /* eqs. (4), (5), (10) */
 
   int32_t m = machine;
-  if (m < 0) {
+  if (m == -1) {
     int32_t best_end = 0;
     m = -1;
     for (int32_t c = 0; c < o_s; ++c) {
@@ -199,25 +215,32 @@ static int place_op(decoder *d, int32_t j, int32_t s, int32_t machine,
         m = c;
       }
     }
-  } else if (m >= o_s) {
-    return ORC_E_INVAL;
   }
+  if (m == -2) {  /* power-aware: the earliest completion after each machine's push-right */
+    int32_t best_end = 0;
+    m = -1;
+    for (int32_t c = 0; c < o_s; ++c) {
+      const int32_t t0c = MAX32(est, free_s[c]), pc = P_AT(in, j, s, c);
+      if (Q_AT(in, j, s, c) > in->q_max) return ORC_E_INFEASIBLE;
+      const int32_t tc = push_right(d, t0c, pc, Q_AT(in, j, s, c));
+      d->work += 3 + (int64_t)(tc - t0c) + pc;
+      if (m < 0 || tc + pc < best_end) {
+        best_end = tc + pc;
+        m = c;
+      }
+    }
+  }
+  if (m < 0 || m >= o_s) return ORC_E_INVAL;
   const int32_t p = P_AT(in, j, s, m), q = Q_AT(in, j, s, m);
   if (q > in->q_max) return ORC_E_INFEASIBLE;
 
   const int32_t t0 = MAX32(est, free_s[m]);  /* eq. (6): after the machine's last op */
-  int32_t t = t0;
-  for (;;) {
-    int64_t last_bad = -1;
-    for (int64_t tau = t; tau < (int64_t)t + p; ++tau)
-      if (d->profile[tau - in->rs] + q > in->q_max) last_bad = tau;
-    if (last_bad < 0) break;
-    t = (int32_t)(last_bad + 1);
-  }
+  const int32_t t = push_right(d, t0, p, q);
   if ((int64_t)t - in->rs + p > d->horizon) abort(); /* horizon bound broken */
   for (int64_t tau = t; tau < (int64_t)t + p; ++tau) d->profile[tau - in->rs] += q;
-  /* every slot of [t0, t+p) needs examining once, then p slots are updated */
-  d->work += (int64_t)(t - t0) + 2 * (int64_t)p;
+  /* every slot of [t0, t+p) needs examining once, then p slots are updated (the
+   * power-aware choice has counted its examinations already) */
+  d->work += machine == -2 ? (int64_t)p : (int64_t)(t - t0) + 2 * (int64_t)p;
 
   free_s[m] = t + p;
   d->done_at[j] = t + p;
@@ -268,11 +291,28 @@ int orc_decode(const orc_instance *in, const int32_t *prio, int64_t *obj,
     free(order);
     return rc;
   }
-  for (int s = 0; s < in->n_stages && rc == ORC_OK; ++s)
-    for (int k = 0; k < n && rc == ORC_OK; ++k) {
-      int32_t j = order[k];
-      if (in->first_stage[j] <= s) rc = place_op(&d, j, s, -1, start, mach);
-    }
+  const int32_t rule_m = (in->decode_rules & ORC_RULE_POWER_ECT) ? -2 : -1;
+  int32_t *stage = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  for (int s = 0; s < in->n_stages && rc == ORC_OK; ++s) {
+    /* the jobs reaching stage s, in priority order ... */
+    int32_t cnt = 0;
+    for (int k = 0; k < n; ++k)
+      if (in->first_stage[order[k]] <= s) stage[cnt++] = order[k];
+    /* ... or (FIFO) by when their previous stage ended, ties kept in priority
+     * order (a stable insertion sort) */
+    if (in->decode_rules & ORC_RULE_FIFO)
+      for (int a = 1; a < cnt; ++a) {
+        const int32_t j = stage[a];
+        int b = a - 1;
+        while (b >= 0 && d.done_at[stage[b]] > d.done_at[j]) {
+          stage[b + 1] = stage[b];
+          --b;
+        }
+        stage[b + 1] = j;
+      }
+    for (int k = 0; k < cnt && rc == ORC_OK; ++k) rc = place_op(&d, stage[k], s, rule_m, start, mach);
+  }
+  free(stage);
   if (rc == ORC_OK) {
     *obj = objective(&d);
     if (work) *work = d.work;

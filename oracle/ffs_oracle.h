@@ -47,7 +47,21 @@ typedef struct {
   int32_t frozen_cmax;         /* max C_j over those jobs (0 if none) */
   int32_t n_active;
   const int32_t *active;       /* [n_active] job ids with first_stage < g; gene k <-> active[k] */
+  int32_t decode_rules;        /* job-vector decode variants, ORC_RULE_* bits (0 = the default) */
 } orc_instance;
+
+/* Variants of the job-vector decode (readings the paper leaves open):
+ * ORC_RULE_FIFO: at each stage the jobs go in order of the completion of
+ *   their previous stage (their `ready` time for the first unfrozen stage),
+ *   earliest first, ties by priority; by default every stage takes the
+ *   priority order.
+ * ORC_RULE_POWER_ECT: the machine of earliest completion counting the power
+ *   push-right on each machine (ties to the lowest index); by default the
+ *   earliest completion ignoring power. Work per op then counts, for every
+ *   machine, 3 + the slots its push-right examines + p, plus p updated.
+ * X/Y chromosomes fix both order and machine and ignore these bits. */
+#define ORC_RULE_FIFO 1
+#define ORC_RULE_POWER_ECT 2
 
 /* Counter-based generator Philox4x64 with 10 rounds (Salmon, Moraes, Dror,
  * Shaw, SC'11), written from its published description. */

@@ -47,6 +47,7 @@ class Instance:
     frozen_tardiness: int
     frozen_cmax: int
     active: np.ndarray       # int32 [n_active]
+    decode_rules: int = 0    # job-vector decode variants: 1 FIFO stage order, 2 power-aware ECT
 
     @property
     def n_active(self) -> int:
@@ -54,7 +55,7 @@ class Instance:
 
     @classmethod
     def from_fields(cls, d: dict) -> "Instance":
-        return cls(**{k: d[k] for k in cls.__dataclass_fields__})
+        return cls(**{k: d[k] for k in cls.__dataclass_fields__ if k in d})
 
 
 @dataclass
@@ -195,6 +196,25 @@ def config1(seed: int = 0) -> Workload:
 def _unrelated(rng, n, speed):
     base = rng.integers(5, 51, size=(n, speed.shape[0]))
     return np.maximum(1, round_half_up(base[:, :, None] * speed[None])).astype(np.int32)
+
+
+def table5_instance(seed: int, n_jobs: int = 10, n_stages: int = 3, machines: int = 2,
+                    q_max: int = 4) -> Instance:
+    """An event-0 instance shaped like the paper's small test (Section 5, Table 5):
+    P_sm ~ U{1..5} the same for every job, Q = 1, R_j ~ U[0, P-bar), D_j = R_j +
+    P-bar * (1 + sigma) with sigma ~ U[0, 2] and P-bar = sum_s mean_m P_sm, WT = 100;
+    10 jobs, 3 stages of 2 machines and a power peak of 4 as in the paper's tests 1-3.
+    Times are integers: R and D are floored / rounded."""
+    rng = np.random.default_rng(seed)
+    p_sm = rng.integers(1, 6, size=(n_stages, machines))
+    proc = np.repeat(p_sm[None], n_jobs, axis=0).astype(np.int32)
+    p_bar = float(p_sm.mean(axis=1).sum())
+    release = np.floor(rng.uniform(0, p_bar, size=n_jobs)).astype(np.int32)
+    sigma = rng.uniform(0, 2, size=n_jobs)
+    due = (release + round_half_up(p_bar * (1 + sigma))).astype(np.int32)
+    nm = np.full(n_stages, machines, np.int32)
+    power = np.ones((n_jobs, n_stages, machines), np.int32)
+    return initial_instance(proc, power, release, due, nm, q_max, 100)
 
 
 def config2(seed: int = 0, generations: int = 500) -> Workload:
