@@ -70,7 +70,21 @@ typedef struct {
                                        set by ffs_prepare and reschedule */
   int32_t n_ops;                    /* host: unfrozen operations R = sum over active jobs of
                                        g - first_stage; set by ffs_prepare and reschedule */
+  int32_t decode_rules;             /* host: FFS_RULE_* bits, variants of the job-priority
+                                       decode (0 = the default rules); reschedule copies it */
 } ffs_instance;
+
+/* Variants of the job-priority decode, readings the paper leaves open (X/Y
+ * chromosomes fix order and machines and ignore them):
+ * FFS_RULE_FIFO: at each stage the jobs go in order of the completion of their
+ *   previous stage (their `ready` time at their first unfrozen stage), earliest
+ *   first, ties by priority; by default every stage takes the priority order.
+ * FFS_RULE_POWER_ECT: each op takes the machine of earliest completion after
+ *   that machine's power push-right (ties to the lowest index); by default the
+ *   earliest completion ignoring power. Its work count per op is, over every
+ *   machine, 3 + the slots its push-right examines + p, plus p updated. */
+#define FFS_RULE_FIFO 1
+#define FFS_RULE_POWER_ECT 2
 
 /* Workspace bytes any ffs_prepare / ffs_status call needs. */
 #define FFS_PREPARE_WORKSPACE 256

@@ -112,6 +112,7 @@ struct DInst {
   const int32_t *active;     // [n]
   int64_t frozen_t;
   int32_t n_jobs, g, om, omp, q_max, wt, rs, nr, n, frozen_cmax, horizon;
+  int32_t rules;  // FFS_RULE_* decode variants (job-priority chromosomes)
 };
 
 template <class T>
@@ -352,13 +353,15 @@ __device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *o
   prof.order();
 
   const int rs = I.rs, cap = prof.cap;
+  const bool power_ect = (I.rules & FFS_RULE_POWER_ECT) != 0, fifo = (I.rules & FFS_RULE_FIFO) != 0;
   int64_t work = 0;
   int32_t *endk = l.gene;  // the genes are no longer needed
   for (int s = 0; s < I.g; ++s) {
     const int os = ld_const(I.nm, s);
     int fr = lane < os ? ld_const(I.mfree, (size_t)s * I.om + lane) : 0;
-    // The stage's ops, compacted in decode order, plus a spare record so the
-    // op loop can prefetch one past the last.
+    // The stage's ops, compacted in decode order (by rank, i.e. priority, or
+    // with FFS_RULE_FIFO by the completion of the previous stage, then rank),
+    // plus a spare record so the op loop can prefetch one past the last.
     int cnt = 0;
     for (int b = 0; b < n; b += kWave) {
       const int x = b + lane;
@@ -366,7 +369,15 @@ __device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *o
       const bool live = x < n && (jf >> 24) <= s;
       const u64 mk = ballot64(live);
       if (live) {
-        const int k = cnt + __popcll(mk & below);
+        int k = cnt + __popcll(mk & below);
+        if (fifo) {
+          const int cx = l.rdy[x];
+          k = 0;
+          for (int y = 0; y < n; ++y) {
+            const int cy = l.rdy[y];
+            k += (l.jobs[y] >> 24) <= s && (cy < cx || (cy == cx && y < x));
+          }
+        }
         const int j = jf & 0xFFFFFF;
         l.op[k] = make_int2(max(rs, l.rdy[x]), (int)((uint32_t)j | ((uint32_t)x << 20)));
         // the packed row is padded to MAXM words: load it whole, keep o_s words
@@ -403,26 +414,48 @@ __device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *o
       const uint32_t key =
           my_machine ? ((uint32_t)(max(o.x, fr) + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane
                      : 0xFFFFFFFFu;
-      const uint32_t kmin =
+      uint32_t kmin =
           (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
+      int t = 0, cw = 0;
+      if (power_ect) {
+        // FFS_RULE_POWER_ECT: each machine's push-right, the earliest completion
+        // after it (ties to the lowest index); every candidate's slots count as work
+        kmin = 0xFFFFFFFFu;
+        for (int m = 0; m < os; ++m) {
+          const uint32_t pqm = (uint32_t)__builtin_amdgcn_readlane((int)pqv, m);
+          const int pm = (int)(pqm & 0xFFFFu);
+          const int t0m = max(o.x, __builtin_amdgcn_readlane(fr, m)) - rs;
+          const int tm = prof.place(t0m, pm, (uint32_t)(I.q_max - (int)(pqm >> 16)));
+          cw += 3 + (tm - t0m) + pm;
+          const uint32_t km = ((uint32_t)(tm + pm + rs) << 4) | (uint32_t)m;
+          if (km < kmin) {
+            kmin = km;
+            t = tm;
+          }
+        }
+      }
       const int mb = (int)(kmin & 15u);
-      const int e = (int)(kmin >> 4);  // completion on mb ignoring power
+      const int e = (int)(kmin >> 4);  // completion on mb (ignoring power, by default)
       const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)pqv, mb);
       const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
-      // Q > Q_max is rejected by the instance checks; even then the unsigned
-      // threshold below only makes every slot pass, so the push-right still ends.
-      const uint32_t thr = (uint32_t)(I.q_max - q);
-      const int t0 = e - p - rs;
-      const int t = prof.place(t0, p, thr);
+      if (!power_ect) {
+        // Q > Q_max is rejected by the instance checks; even then the unsigned
+        // threshold only makes every slot pass, so the push-right still ends.
+        const int t0 = e - p - rs;
+        t = prof.place(t0, p, (uint32_t)(I.q_max - q));
+        cw = (t - t0) + 2 * p;
+      } else {
+        cw += p;
+      }
       prof.commit(t, p, q);
       const int end = t + p + rs;
       fr = lane == mb ? end : fr;
       endk[k] = PLAN ? end | (mb << 27) : end;
-      stage_work += end - e + 2 * p;  // (t - t0) + 2p
+      stage_work += cw;
       o = o_next;
       pqv = pq_next;
     }
-    work += (int64_t)stage_work + 3 * os * cnt;
+    work += (int64_t)stage_work + (power_ect ? 0 : 3 * os * cnt);
     if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
     // Completion times back to the jobs; start and machine of every op.
@@ -2005,6 +2038,7 @@ DInst make_dinst(const ffs_instance *in, const uint32_t *pq) {
   d.n = in->n_active;
   d.frozen_cmax = in->frozen_cmax;
   d.horizon = in->horizon;
+  d.rules = in->decode_rules;
   return d;
 }
 
@@ -2854,6 +2888,7 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
   next->n_active = host.n_active;
   next->horizon = (int32_t)host.horizon;
   next->n_ops = host.n_ops;
+  next->decode_rules = prev->decode_rules;
   return check_host(next);
 }
 

@@ -44,8 +44,12 @@ class FfsInstance(ctypes.Structure):
         ("n_running", ctypes.c_int32), ("running", _vp),
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
         ("n_active", ctypes.c_int32), ("active", _vp),
-        ("horizon", ctypes.c_int32), ("n_ops", ctypes.c_int32),
+        ("horizon", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("decode_rules", ctypes.c_int32),
     ]
+
+
+RULE_FIFO = 1        # FFS_RULE_FIFO: each stage in order of the previous stage's completion
+RULE_POWER_ECT = 2   # FFS_RULE_POWER_ECT: machine of earliest completion after the push-right
 
 
 class FfsGaParams(ctypes.Structure):
@@ -164,7 +168,8 @@ class DeviceInstance:
             _dptr(t["release"]), _dptr(t["due"]), int(inst.q_max), int(inst.wt), int(inst.rs),
             _dptr(t["first_stage"]), _dptr(t["ready"]), _dptr(t["machine_free"]),
             int(len(inst.running)), _dptr(t["running"]), int(inst.frozen_tardiness),
-            int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0, 0)
+            int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0, 0,
+            int(getattr(inst, "decode_rules", 0)))
         d = cls(s, t)
         if prepare:
             d.prepare(workspace)
@@ -196,7 +201,7 @@ class DeviceInstance:
         out["running"] = out["running"][:s.n_running].reshape(-1, 2)
         out["active"] = out["active"][:s.n_active]
         for k in ("n_jobs", "n_stages", "o_max", "q_max", "wt", "rs", "frozen_tardiness",
-                  "frozen_cmax", "horizon", "n_ops"):
+                  "frozen_cmax", "horizon", "n_ops", "decode_rules"):
             out[k] = int(getattr(s, k))
         n = out["n_jobs"]
         for k in ("proc", "power"):
