@@ -407,6 +407,9 @@ def main():
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "batch", "serve", "surrogate", "large"])
     ap.add_argument("--lds-slots", type=int, default=0)
+    ap.add_argument("--rules", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="paper workload: job-vector decode variants, bit 0 FIFO stage order, "
+                         "bit 1 power-aware machine choice")
     ap.add_argument("--encoding", default="job", choices=["job", "xy"],
                     help="paper workload: one priority per job (default) or the paper's X/Y "
                          "machine and priority matrices")
@@ -461,9 +464,11 @@ def bench_paper(args):
     if args.generations is not None:
         wl.generations = args.generations
     xy = args.encoding == "xy"
+    import dataclasses
     if xy:
-        import dataclasses
         wl.ga = dataclasses.replace(wl.ga, encoding=1)
+    if args.rules:
+        wl.initial = dataclasses.replace(wl.initial, decode_rules=args.rules)
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -527,6 +532,7 @@ def bench_paper(args):
                         "5 arrival events, 32 islands x 8x16 = 4096, 500 generations/event" +
                         (", X/Y chromosome (machine and priority per operation)" if xy else ""),
             "encoding": "xy" if xy else "job priority vector",
+            "decode_rules": args.rules,
             "decodes_per_step": decodes // args.steps,
             "events": 1 + len(wl.arrivals),
             "best_obj_per_event": best,

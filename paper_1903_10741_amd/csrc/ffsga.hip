@@ -312,10 +312,13 @@ __device__ __forceinline__ int wave_max32(int v) {
 // completion, lowest index on ties; the push-right reads 64 profile slots at
 // once and a ballot marks those that would break the peak; the scalar unit
 // moves the start past the last of them inside the window.
-template <int MAXM, bool PLAN, class Prof>
-__device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *obj_out,
-                           int64_t *work_out, int32_t *start_out, int32_t *mach_out,
-                           int32_t *span_max = nullptr) {
+//
+// RULES: false compiles the default rules only (no per-op rule test);
+// true reads I.rules (FFS_RULE_*). decode_core picks once per decode.
+template <int MAXM, bool PLAN, bool RULES, class Prof>
+__device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int64_t *obj_out,
+                                 int64_t *work_out, int32_t *start_out, int32_t *mach_out,
+                                 int32_t *span_max) {
   const int lane = __lane_id();
   const int n = I.n;
   const u64 below = (1ull << lane) - 1;
@@ -353,7 +356,8 @@ __device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *o
   prof.order();
 
   const int rs = I.rs, cap = prof.cap;
-  const bool power_ect = (I.rules & FFS_RULE_POWER_ECT) != 0, fifo = (I.rules & FFS_RULE_FIFO) != 0;
+  const bool power_ect = RULES && (I.rules & FFS_RULE_POWER_ECT) != 0;
+  const bool fifo = RULES && (I.rules & FFS_RULE_FIFO) != 0;
   int64_t work = 0;
   int32_t *endk = l.gene;  // the genes are no longer needed
   for (int s = 0; s < I.g; ++s) {
@@ -490,6 +494,18 @@ __device__ int decode_core(const DInst &I, const Lds &l, Prof &&prof, int64_t *o
     if (work_out) *work_out = work;
   }
   return kDecOk;
+}
+
+template <int MAXM, bool PLAN, class Prof>
+__device__ __forceinline__ int decode_core(const DInst &I, const Lds &l, Prof &&prof,
+                                           int64_t *obj_out, int64_t *work_out,
+                                           int32_t *start_out, int32_t *mach_out,
+                                           int32_t *span_max = nullptr) {
+  if (I.rules == 0)
+    return decode_core_rules<MAXM, PLAN, false>(I, l, prof, obj_out, work_out, start_out, mach_out,
+                                                span_max);
+  return decode_core_rules<MAXM, PLAN, true>(I, l, prof, obj_out, work_out, start_out, mach_out,
+                                             span_max);
 }
 
 __device__ void flag_error(Header *h, int status) {
