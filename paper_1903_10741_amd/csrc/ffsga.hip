@@ -49,6 +49,10 @@ constexpr int kDefaultLdsSlots = 4096;
 constexpr int kFixBlocks = 64;       // overflow decodes in flight at once
 constexpr int kHeaderBytes = 256;
 constexpr int kMaxTime = 1 << 27;    // completion times pack as (time << 4 | machine)
+// Free time of the lanes that hold no machine of the stage: their machine key
+// (kNoMachine + p) << 4 | lane stays above every real key and below 2^32.
+constexpr int kNoMachine = 0x0FFF0000;
+static_assert(kNoMachine >= kMaxTime && kNoMachine + 0xFFFF < (1 << 28), "machine key");
 
 // Device-side status word and small results at the head of every workspace.
 struct Header {
@@ -93,6 +97,9 @@ __device__ __forceinline__ uint32_t draw_below(u64 w, uint32_t n) {
   return (uint32_t)(((w >> 32) * (u64)n) >> 32);
 }
 
+// v_writelane: a uniform value into one lane of a register (bound to the LLVM
+// intrinsic by name; hipcc has no builtin for it).
+extern "C" __device__ int ffs_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Lane mask of a predicate across the wave.
@@ -211,7 +218,8 @@ __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint
 // Commit q on [t, t + p) of a byte profile. The lanes cover the word-aligned
 // slots [base, base + 64): each quad of lanes holds one profile word, sums its
 // four byte increments (no carries: every byte stays <= Q_max) and its first
-// lane adds the word, so no two lanes add to one word. Slots past cap (the
+// lane adds the word, so no two lanes add to one word (quads outside the window
+// add zero: cheaper than testing for it). Slots past cap (the
 // decode is then redone off chip) are clamped onto the last word, so the zero
 // slots after cap stay zero.
 template <class Prof>
@@ -221,7 +229,7 @@ __device__ __forceinline__ void commit_bytes(const Prof &prof, int t, int p, int
   uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
   c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
   c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);
-  if ((lane & 3) == 0 && c != 0u) prof.add_word(min(base + lane, cap - 4), c);
+  if ((lane & 3) == 0) prof.add_word(min(base + lane, cap - 4), c);
   if (t - base + p > kWave)  // windows longer than the lanes
     for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
   prof.order();
@@ -246,11 +254,12 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //   gene  [n]        the chromosome (input)
 //   jobs  [n]        by rank: job | first_stage << 24  (correction scratch before decode)
 //   rdy   [n]        by rank: completion of the job's last placed stage
-//   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20)
+//   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20);
+//                    a placed op's earliest start is overwritten by its end time
 //   rec   [n+1][o_s] the current stage's packed P | Q << 16 rows, one word per machine
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
-// gene is free once the ranks are built and holds the stage's end times.
+// gene is free once the ranks are built.
 struct Lds {
   int32_t *gene, *jobs, *rdy;
   int2 *op;
@@ -359,10 +368,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   const bool power_ect = RULES && (I.rules & FFS_RULE_POWER_ECT) != 0;
   const bool fifo = RULES && (I.rules & FFS_RULE_FIFO) != 0;
   int64_t work = 0;
-  int32_t *endk = l.gene;  // the genes are no longer needed
   for (int s = 0; s < I.g; ++s) {
     const int os = ld_const(I.nm, s);
-    int fr = lane < os ? ld_const(I.mfree, (size_t)s * I.om + lane) : 0;
+    int fr = lane < os ? ld_const(I.mfree, (size_t)s * I.om + lane) : kNoMachine;
     // The stage's ops, compacted in decode order (by rank, i.e. priority, or
     // with FFS_RULE_FIFO by the completion of the previous stage, then rank),
     // plus a spare record so the op loop can prefetch one past the last.
@@ -403,9 +411,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     if (lane < os) l.rec[cnt * os + lane] = 0;
     if (lane == 0) l.op[cnt] = make_int2(0, 0);
     __asm__ volatile("" ::: "memory");
-    const bool my_machine = lane < os;
     const uint32_t *recp = l.rec + min(lane, os - 1);
-    const int2 *opp = l.op;
+    int2 *opp = l.op;
     int2 o = *opp;
     uint32_t pqv = *recp;
     int stage_work = 0;
@@ -415,9 +422,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const int2 o_next = *opp;
       const uint32_t pq_next = *recp;
       // Machine of earliest completion (ties to the lowest index).
-      const uint32_t key =
-          my_machine ? ((uint32_t)(max(o.x, fr) + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane
-                     : 0xFFFFFFFFu;
+      const uint32_t key = ((uint32_t)(max(o.x, fr) + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
       uint32_t kmin =
           (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
       int t = 0, cw = 0;
@@ -453,8 +458,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       }
       prof.commit(t, p, q);
       const int end = t + p + rs;
-      fr = lane == mb ? end : fr;
-      endk[k] = PLAN ? end | (mb << 27) : end;
+      fr = ffs_writelane(end, mb, fr);
+      opp[-1].x = PLAN ? end | (mb << 27) : end;
       stage_work += cw;
       o = o_next;
       pqv = pq_next;
@@ -464,8 +469,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     __asm__ volatile("" ::: "memory");
     // Completion times back to the jobs; start and machine of every op.
     for (int k = lane; k < cnt; k += kWave) {
-      const uint32_t jx = (uint32_t)l.op[k].y;
-      const int e = endk[k];
+      const int2 oe = l.op[k];
+      const uint32_t jx = (uint32_t)oe.y;
+      const int e = oe.x;
       const int end = PLAN ? e & (kMaxTime - 1) : e, mb = PLAN ? e >> 27 : 0;
       l.rdy[jx >> 20] = end;
       if (PLAN) {
