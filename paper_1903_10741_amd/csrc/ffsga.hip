@@ -199,18 +199,20 @@ struct GlobalProfile {
 template <class Prof>
 __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint32_t thr) {
   const int lane = __lane_id(), cap = prof.cap;
-  int t = t0, scan = min(t0, cap);
-  uint32_t v = prof.get(scan + lane);
+  int t = t0, top = min(t0, cap) + kWave;  // the chunk is [top - 64, top)
+  int sl = top - kWave + lane;              // this lane's slot
+  uint32_t v = prof.get(sl);
   for (;;) {
     // slots of [t, t + p) in this chunk (one unsigned compare) that break the peak
-    const u64 hit = ballot64((uint32_t)(scan + lane - t) < (uint32_t)p) & ballot64(v > thr);
+    const u64 hit = ballot64((uint32_t)(sl - t) < (uint32_t)p) & ballot64(v > thr);
     if (hit) {
-      t = scan + (kWave - __clzll(hit));
+      t = top - (int)__clzll(hit);
       continue;
     }
-    if (t + p <= scan + kWave || scan + kWave >= cap) break;
-    scan += kWave;
-    v = prof.get(scan + lane);
+    if (t + p <= top || top >= cap) break;
+    top += kWave;
+    sl += kWave;
+    v = prof.get(sl);
   }
   return t;
 }
@@ -412,7 +414,12 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     if (lane == 0) l.op[cnt] = make_int2(0, 0);
     __asm__ volatile("" ::: "memory");
     const uint32_t *recp = l.rec + min(lane, os - 1);
-    int2 *opp = l.op;
+    // The record pointer as a per-lane value (the asm hides that the zero is
+    // uniform): records are then read and written through one vector address
+    // with immediate offsets instead of a scalar address moved in every op.
+    int vz;
+    __asm__("v_mov_b32 %0, 0" : "=v"(vz));
+    int2 *opp = l.op + vz;
     int2 o = *opp;
     uint32_t pqv = *recp;
     int stage_work = 0;
@@ -422,7 +429,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const int2 o_next = *opp;
       const uint32_t pq_next = *recp;
       // Machine of earliest completion (ties to the lowest index).
-      const uint32_t key = ((uint32_t)(max(o.x, fr) + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
+      const int mx = max(o.x, fr);
+      const int t0v = mx - rs;  // earliest start on this lane's machine, slots after RS
+      const uint32_t key = ((uint32_t)(mx + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
       uint32_t kmin =
           (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
       int t = 0, cw = 0;
@@ -430,10 +439,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // FFS_RULE_POWER_ECT: each machine's push-right, the earliest completion
         // after it (ties to the lowest index); every candidate's slots count as work
         kmin = 0xFFFFFFFFu;
+        const int ox = uni(o.x);  // uniform: keeps this loop on the scalar unit
         for (int m = 0; m < os; ++m) {
           const uint32_t pqm = (uint32_t)__builtin_amdgcn_readlane((int)pqv, m);
           const int pm = (int)(pqm & 0xFFFFu);
-          const int t0m = max(o.x, __builtin_amdgcn_readlane(fr, m)) - rs;
+          const int t0m = max(ox, __builtin_amdgcn_readlane(fr, m)) - rs;
           const int tm = prof.place(t0m, pm, (uint32_t)(I.q_max - (int)(pqm >> 16)));
           cw += 3 + (tm - t0m) + pm;
           const uint32_t km = ((uint32_t)(tm + pm + rs) << 4) | (uint32_t)m;
@@ -444,13 +454,12 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         }
       }
       const int mb = (int)(kmin & 15u);
-      const int e = (int)(kmin >> 4);  // completion on mb (ignoring power, by default)
       const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)pqv, mb);
       const int p = (int)(pq & 0xFFFFu), q = (int)(pq >> 16);
       if (!power_ect) {
         // Q > Q_max is rejected by the instance checks; even then the unsigned
         // threshold only makes every slot pass, so the push-right still ends.
-        const int t0 = e - p - rs;
+        const int t0 = __builtin_amdgcn_readlane(t0v, mb);
         t = prof.place(t0, p, (uint32_t)(I.q_max - q));
         cw = (t - t0) + 2 * p;
       } else {
