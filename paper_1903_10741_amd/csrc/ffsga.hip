@@ -949,10 +949,16 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
 // earliest power-feasible start after its job's previous stage and the
 // machine's last op, as in decode_core. Every lane calls this; the result is
 // uniform; on kDecOk lane 0 has written *obj_out.
-template <bool PLAN, class Prof>
-__device__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l, Prof &&prof,
-                              int64_t *obj_out, int64_t *work_out, int32_t *start_out,
-                              int32_t *mach_out) {
+//
+// REG: the jobs' ready times and the machines' free times live in registers
+// (lane x of rv0 / rv1 holds job x / 64 + x, lane f of fmv machine f), read
+// with readlane and written with writelane, so an op waits on no LDS read but
+// its profile chunk; needs at most 128 active jobs and 64 machine slots
+// (g * o_max). Otherwise they live in LDS and are read one op ahead.
+template <bool PLAN, bool REG, class Prof>
+__device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, Prof &&prof,
+                                int64_t *obj_out, int64_t *work_out, int32_t *start_out,
+                                int32_t *mach_out) {
   const int lane = __lane_id(), n = I.n, R = T.R;
   for (int y = lane; y <= R; y += kWave) l.head[y] = 0;
   __asm__ volatile("" ::: "memory");
@@ -1003,8 +1009,15 @@ __device__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l, Pr
     }
     base += __builtin_amdgcn_readlane(incl, kWave - 1);
   }
-  for (int x = lane; x < n; x += kWave) l.rdy[x] = ld_const(I.ready, ld_const(I.active, x));
-  for (int x = lane; x < I.g * I.om; x += kWave) l.fm[x] = ld_const(I.mfree, x);
+  int rv0 = 0, rv1 = 0, fmv = 0;
+  if constexpr (REG) {
+    if (lane < n) rv0 = ld_const(I.ready, ld_const(I.active, lane));
+    if (kWave + lane < n) rv1 = ld_const(I.ready, ld_const(I.active, kWave + lane));
+    if (lane < I.g * I.om) fmv = ld_const(I.mfree, lane);
+  } else {
+    for (int x = lane; x < n; x += kWave) l.rdy[x] = ld_const(I.ready, ld_const(I.active, x));
+    for (int x = lane; x < I.g * I.om; x += kWave) l.fm[x] = ld_const(I.mfree, x);
+  }
   prof.clear();
   prof.order();
   for (int r = 0; r < I.nr; ++r) {
@@ -1015,37 +1028,64 @@ __device__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l, Pr
   prof.order();
   __asm__ volatile("" ::: "memory");
 
-  // Ops in Z order. The next op's record, job-ready and machine-free times
-  // are read one op ahead; an op that frees the next op's job or machine
-  // hands its end over directly.
+  // Ops in Z order, the next op's record read one op ahead.
   const int rs = I.rs, cap = prof.cap;
   int64_t work = 0;
   int max_end = rs;
   int2 rec = R > 0 ? l.zrec[0] : make_int2(0, 0);
-  int rdy_n = l.rdy[uni(rec.x) & 0xFFF], fm_n = l.fm[uni(rec.x) >> 12];
-  for (int z = 0; z < R; ++z) {
-    const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
-    const int est = max(rs, uni(rdy_n)), fr = uni(fm_n);
-    rec = l.zrec[min(z + 1, R - 1)];
-    const int xfn = uni(rec.x), xn = xfn & 0xFFF, fn = xfn >> 12;
-    rdy_n = l.rdy[xn];
-    fm_n = l.fm[fn];
-    const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
-    const uint32_t thr = (uint32_t)(I.q_max - q);
-    const int t0 = max(est, fr) - rs;
-    const int t = prof.place(t0, p, thr);
-    prof.commit(t, p, q);
-    const int end = t + p + rs;
-    l.rdy[x] = end;
-    l.fm[f] = end;
-    if (xn == x) rdy_n = end;
-    if (fn == f) fm_n = end;
-    work += (int64_t)(t - t0) + 2 * p;
-    max_end = max(max_end, end);
-    if (PLAN && lane == 0) {
-      const int j = ld_const(I.active, x), s = f / I.om;
-      start_out[(size_t)j * I.g + s] = t + rs;
-      mach_out[(size_t)j * I.g + s] = f - s * I.om;
+  if constexpr (REG) {
+    for (int z = 0; z < R; ++z) {
+      const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
+      rec = l.zrec[min(z + 1, R - 1)];
+      const int rd = x < kWave ? __builtin_amdgcn_readlane(rv0, x)
+                               : __builtin_amdgcn_readlane(rv1, x - kWave);
+      const int est = max(rs, rd), fr = __builtin_amdgcn_readlane(fmv, f);
+      const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
+      const int t0 = max(est, fr) - rs;
+      const int t = prof.place(t0, p, (uint32_t)(I.q_max - q));
+      prof.commit(t, p, q);
+      const int end = t + p + rs;
+      if (x < kWave) rv0 = ffs_writelane(end, x, rv0);
+      else rv1 = ffs_writelane(end, x - kWave, rv1);
+      fmv = ffs_writelane(end, f, fmv);
+      work += (int64_t)(t - t0) + 2 * p;
+      max_end = max(max_end, end);
+      if (PLAN && lane == 0) {
+        const int j = ld_const(I.active, x), s = f / I.om;
+        start_out[(size_t)j * I.g + s] = t + rs;
+        mach_out[(size_t)j * I.g + s] = f - s * I.om;
+      }
+    }
+    if (lane < n) l.rdy[lane] = rv0;
+    if (kWave + lane < n) l.rdy[kWave + lane] = rv1;
+  } else {
+    // The next op's job-ready and machine-free times are read one op ahead too;
+    // an op that frees the next op's job or machine hands its end over directly.
+    int rdy_n = l.rdy[uni(rec.x) & 0xFFF], fm_n = l.fm[uni(rec.x) >> 12];
+    for (int z = 0; z < R; ++z) {
+      const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
+      const int est = max(rs, uni(rdy_n)), fr = uni(fm_n);
+      rec = l.zrec[min(z + 1, R - 1)];
+      const int xfn = uni(rec.x), xn = xfn & 0xFFF, fn = xfn >> 12;
+      rdy_n = l.rdy[xn];
+      fm_n = l.fm[fn];
+      const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
+      const uint32_t thr = (uint32_t)(I.q_max - q);
+      const int t0 = max(est, fr) - rs;
+      const int t = prof.place(t0, p, thr);
+      prof.commit(t, p, q);
+      const int end = t + p + rs;
+      l.rdy[x] = end;
+      l.fm[f] = end;
+      if (xn == x) rdy_n = end;
+      if (fn == f) fm_n = end;
+      work += (int64_t)(t - t0) + 2 * p;
+      max_end = max(max_end, end);
+      if (PLAN && lane == 0) {
+        const int j = ld_const(I.active, x), s = f / I.om;
+        start_out[(size_t)j * I.g + s] = t + rs;
+        mach_out[(size_t)j * I.g + s] = f - s * I.om;
+      }
     }
   }
   if (max_end - rs > cap) return kDecOverflow;
@@ -1065,6 +1105,15 @@ __device__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l, Pr
     if (work_out) *work_out = work;
   }
   return kDecOk;
+}
+
+template <bool PLAN, class Prof>
+__device__ __forceinline__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l,
+                                              Prof &&prof, int64_t *obj_out, int64_t *work_out,
+                                              int32_t *start_out, int32_t *mach_out) {
+  if (I.n <= 2 * kWave && I.g * I.om <= kWave)
+    return decode_xy_core_t<PLAN, true>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
+  return decode_xy_core_t<PLAN, false>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
 }
 
 // Gene/op table of an instance (one block of 1024 threads): the active jobs'

@@ -56,6 +56,36 @@ def test_decode_xy_matches_oracle():
                 assert (start[i] == st).all() and (mach[i] == mc).all()
 
 
+@pytest.mark.parametrize("n_jobs,machines,why", [
+    (64, 3, "64 jobs: ready times in one register"),
+    (100, [2, 3, 3, 2], "65-128 jobs: the second register"),
+    (150, 2, "more than 128 jobs: ready times in LDS"),
+    (20, [16, 3, 16, 5, 2], "more than 64 machine slots: free times in LDS")])
+def test_decode_xy_state_layouts(n_jobs, machines, why):
+    """Each home of the job-ready and machine-free state (registers or LDS),
+    at event 0 and after an arrival, against the oracle."""
+    torch, ffsga = _ffs()
+    base = W.random_instance(17, n_jobs=n_jobs, n_stages=len(machines) if isinstance(machines, list)
+                             else 3, machines=machines, p_max=30, percent=55)
+    st, mc = oracle.decode(base, W.random_population(1, 1, base.n_active)[0], want_schedule=True)[1:3]
+    arr = W.random_arrival(5, base, 40, 9, p_max=30)
+    later = W.Instance.from_fields(oracle.reschedule(base, st, mc, arr.rs, arr.proc, arr.power,
+                                                     arr.release, arr.due))
+    for name, inst in (("event 0", base), ("event 1", later)):
+        _say("decode_xy", why, name, "n_active", inst.n_active)
+        d = ffsga.DeviceInstance.from_host(inst)
+        genes = W.random_xy_population(3, 64, inst)
+        got = ffsga.ffs_decode(d, torch.from_numpy(genes).cuda(), want_schedule=True,
+                               want_work=True, xy=True)
+        obj, work = oracle.decode_xy_pop(inst, genes, n_threads=8, want_work=True)
+        assert (got["obj"].cpu().numpy() == obj).all()
+        assert (got["work"].cpu().numpy() == work).all()
+        start, mach = got["start"].cpu().numpy(), got["mach"].cpu().numpy()
+        for i in (0, 63):
+            _, st2, mc2, _ = oracle.decode_xy(inst, genes[i], want_schedule=True)
+            assert (start[i] == st2).all() and (mach[i] == mc2).all()
+
+
 def test_decode_xy_table4_example():
     """The printed X(k) and Y(k) of Section 4.3 give Fig. 8's makespan on the GPU."""
     torch, ffsga = _ffs()
