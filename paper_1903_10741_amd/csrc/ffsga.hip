@@ -950,12 +950,12 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
 // machine's last op, as in decode_core. Every lane calls this; the result is
 // uniform; on kDecOk lane 0 has written *obj_out.
 //
-// REG: the jobs' ready times and the machines' free times live in registers
-// (lane x of rv0 / rv1 holds job x / 64 + x, lane f of fmv machine f), read
-// with readlane and written with writelane, so an op waits on no LDS read but
-// its profile chunk; needs at most 128 active jobs and 64 machine slots
-// (g * o_max). Otherwise they live in LDS and are read one op ahead.
-template <bool PLAN, bool REG, class Prof>
+// NB = 1 or 2: the jobs' ready times and the machines' free times live in
+// registers (lane x of rv0 / rv1 holds job x / 64 + x, lane f of fmv machine
+// f), read with readlane and written with writelane, so an op waits on no LDS
+// read but its profile chunk; needs at most 64 * NB active jobs and 64 machine
+// slots (g * o_max). NB = 0: they live in LDS and are read one op ahead.
+template <bool PLAN, int NB, class Prof>
 __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, Prof &&prof,
                                 int64_t *obj_out, int64_t *work_out, int32_t *start_out,
                                 int32_t *mach_out) {
@@ -1010,9 +1010,9 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     base += __builtin_amdgcn_readlane(incl, kWave - 1);
   }
   int rv0 = 0, rv1 = 0, fmv = 0;
-  if constexpr (REG) {
+  if constexpr (NB > 0) {
     if (lane < n) rv0 = ld_const(I.ready, ld_const(I.active, lane));
-    if (kWave + lane < n) rv1 = ld_const(I.ready, ld_const(I.active, kWave + lane));
+    if (NB > 1 && kWave + lane < n) rv1 = ld_const(I.ready, ld_const(I.active, kWave + lane));
     if (lane < I.g * I.om) fmv = ld_const(I.mfree, lane);
   } else {
     for (int x = lane; x < n; x += kWave) l.rdy[x] = ld_const(I.ready, ld_const(I.active, x));
@@ -1033,22 +1033,25 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   int64_t work = 0;
   int max_end = rs;
   int2 rec = R > 0 ? l.zrec[0] : make_int2(0, 0);
-  if constexpr (REG) {
+  if constexpr (NB > 0) {
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
       rec = l.zrec[min(z + 1, R - 1)];
-      const int rd = x < kWave ? __builtin_amdgcn_readlane(rv0, x)
-                               : __builtin_amdgcn_readlane(rv1, x - kWave);
-      const int est = max(rs, rd), fr = __builtin_amdgcn_readlane(fmv, f);
+      const int xl = x & (kWave - 1);
+      // both registers read and written, the right one chosen: no branch
+      const int r0 = __builtin_amdgcn_readlane(rv0, xl);
+      const int r1 = NB > 1 ? __builtin_amdgcn_readlane(rv1, xl) : 0;
+      const bool hi = NB > 1 && x >= kWave;
+      const int est = max(rs, hi ? r1 : r0), fr = __builtin_amdgcn_readlane(fmv, f);
       const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
       const int t0 = max(est, fr) - rs;
       const int t = prof.place(t0, p, (uint32_t)(I.q_max - q));
       prof.commit(t, p, q);
       const int end = t + p + rs;
-      if (x < kWave) rv0 = ffs_writelane(end, x, rv0);
-      else rv1 = ffs_writelane(end, x - kWave, rv1);
+      rv0 = ffs_writelane(hi ? r0 : end, xl, rv0);
+      if (NB > 1) rv1 = ffs_writelane(hi ? end : r1, xl, rv1);
       fmv = ffs_writelane(end, f, fmv);
-      work += (int64_t)(t - t0) + 2 * p;
+      work += (uint32_t)((t - t0) + 2 * p);  // non-negative
       max_end = max(max_end, end);
       if (PLAN && lane == 0) {
         const int j = ld_const(I.active, x), s = f / I.om;
@@ -1057,7 +1060,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
       }
     }
     if (lane < n) l.rdy[lane] = rv0;
-    if (kWave + lane < n) l.rdy[kWave + lane] = rv1;
+    if (NB > 1 && kWave + lane < n) l.rdy[kWave + lane] = rv1;
   } else {
     // The next op's job-ready and machine-free times are read one op ahead too;
     // an op that frees the next op's job or machine hands its end over directly.
@@ -1111,9 +1114,11 @@ template <bool PLAN, class Prof>
 __device__ __forceinline__ int decode_xy_core(const DInst &I, const XyTab &T, const LdsXy &l,
                                               Prof &&prof, int64_t *obj_out, int64_t *work_out,
                                               int32_t *start_out, int32_t *mach_out) {
-  if (I.n <= 2 * kWave && I.g * I.om <= kWave)
-    return decode_xy_core_t<PLAN, true>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
-  return decode_xy_core_t<PLAN, false>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
+  if (I.g * I.om <= kWave && I.n <= kWave)
+    return decode_xy_core_t<PLAN, 1>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
+  if (I.g * I.om <= kWave && I.n <= 2 * kWave)
+    return decode_xy_core_t<PLAN, 2>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
+  return decode_xy_core_t<PLAN, 0>(I, T, l, prof, obj_out, work_out, start_out, mach_out);
 }
 
 // Gene/op table of an instance (one block of 1024 threads): the active jobs'
