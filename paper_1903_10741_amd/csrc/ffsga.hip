@@ -1486,11 +1486,16 @@ __device__ void replace_island(int32_t *prio, int64_t *obj, int32_t *elite, int6
   if (threadIdx.x == 0) obj[base + w] = elite_obj[I];
 }
 
-__global__ __launch_bounds__(256) void replace_kernel(int32_t *prio, int64_t *obj, int32_t *elite,
-                                                      int64_t *elite_obj, int K, int n) {
-  __shared__ int64_t sv[256];
-  __shared__ int si[256];
-  replace_island(prio, obj, elite, elite_obj, blockIdx.x, K, n, sv, si);
+// Elitist replacement of every island, one wave per island (replace_island_wave).
+__global__ __launch_bounds__(64) void replace_wave_kernel(int32_t *prio, int64_t *obj,
+                                                          int32_t *elite, int64_t *elite_obj, int K,
+                                                          int n) {
+  GaDev A{};
+  A.prio_out = prio;
+  A.obj_out = obj;
+  A.elite = elite;
+  A.elite_obj = elite_obj;
+  replace_island_wave(A, blockIdx.x, K, n);
 }
 
 __global__ __launch_bounds__(256) void elite_init_kernel(const int32_t *prio, const int64_t *obj,
@@ -2432,8 +2437,8 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     if (e != hipSuccess) return FFS_E_DEVICE;
     int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream, xy);
     if (rc) return rc;
-    if (launch(2, replace_kernel, dim3(ga->params.islands), dim3(256), 0, stream, L.prio[1 - cur],
-               L.obj[1 - cur], L.elite, L.elite_obj, K, n) != hipSuccess)
+    if (launch(2, replace_wave_kernel, dim3(ga->params.islands), dim3(kWave), 0, stream,
+               L.prio[1 - cur], L.obj[1 - cur], L.elite, L.elite_obj, K, n) != hipSuccess)
       return FFS_E_DEVICE;
     const ffs_ga_params &p = ga->params;
     if (p.mig_interval > 0 && p.mig_k > 0 && p.islands > 1 && gen % p.mig_interval == 0) {
