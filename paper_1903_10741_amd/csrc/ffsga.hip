@@ -713,15 +713,27 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
     lead = i - (r & 1) * A.cols;
     partner = (r & 1) ? i - A.cols : i + A.cols;
   }
+  // The crossover block (lane 0: the pair leader's purpose 1) and the mutation
+  // block (other lanes: this slot's purpose 2) in one vector evaluation: the
+  // scalar unit, which the CU's waves share, is the busier one.
+  u64 dw[4];
+  {
+    const bool xl = lane == 0;
+    philox((u64)(xl ? lead : i), (u64)gen, (u64)A.event,
+           ((xl ? 1ull : 2ull) << 32) | (u64)variant, A.seed, A.shop, dw);
+  }
+  const uint32_t xw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 0);
+  const uint32_t xw1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[1] >> 32), 0);
+  const uint32_t mw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 1);
+  const uint32_t mw1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[1] >> 32), 1);
+  const uint32_t mw2 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[2] >> 32), 1);
   const int w_self = select_winner(A, i);
   const int32_t *mine = A.prio_in + (size_t)w_self * n;
   bool cross = false;
   int cut = n;
   if (lead >= 0 && n >= 2) {
-    u64 w[4];
-    philox((u64)lead, (u64)gen, (u64)A.event, (1ull << 32) | (u64)variant, A.seed, A.shop, w);
-    cross = (uint32_t)(w[0] >> 32) < A.pc;
-    cut = 1 + (int)draw_below(w[1], (uint32_t)(n - 1));
+    cross = xw0 < A.pc;
+    cut = 1 + (int)draw_below((u64)xw1 << 32, (uint32_t)(n - 1));
   }
   if (cross) {
     const int32_t *other = A.prio_in + (size_t)select_winner(A, partner) * n;
@@ -733,11 +745,9 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
     __asm__ volatile("" ::: "memory");
   }
   if (n >= 2) {  // swap mutation (Fig. 12)
-    u64 w[4];
-    philox((u64)i, (u64)gen, (u64)A.event, (2ull << 32) | (u64)variant, A.seed, A.shop, w);
-    if ((uint32_t)(w[0] >> 32) < A.pm) {
-      const int x = (int)draw_below(w[1], (uint32_t)n);
-      int y = (int)draw_below(w[2], (uint32_t)(n - 1));
+    if (mw0 < A.pm) {
+      const int x = (int)draw_below((u64)mw1 << 32, (uint32_t)n);
+      int y = (int)draw_below((u64)mw2 << 32, (uint32_t)(n - 1));
       y += y >= x;
       if (lane == 0) {
         const int gx = l.gene[x];
@@ -1272,14 +1282,24 @@ __device__ void breed_child_xy(const GaDev &A, const DInst &I, const XyTab &T, i
     lead = i - (r & 1) * A.cols;
     partner = (r & 1) ? i - A.cols : i + A.cols;
   }
+  // crossover block on lane 0, mutation block on the others (as in breed_child)
+  u64 dw[4];
+  {
+    const bool xl = lane == 0;
+    philox((u64)(xl ? lead : i), (u64)gen, (u64)A.event,
+           ((xl ? 1ull : 2ull) << 32) | (u64)variant, A.seed, A.shop, dw);
+  }
+  const uint32_t xw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 0);
+  const uint32_t xw1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[1] >> 32), 0);
+  const uint32_t mw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 1);
+  const uint32_t mw1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[1] >> 32), 1);
+  const uint32_t mw2 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[2] >> 32), 1);
   const int32_t *mine = A.prio_in + (size_t)select_winner(A, i) * L;
   bool cross = false;
   int cut = R;
   if (lead >= 0 && R >= 2) {
-    u64 w[4];
-    philox((u64)lead, (u64)gen, (u64)A.event, (1ull << 32) | (u64)variant, A.seed, A.shop, w);
-    cross = (uint32_t)(w[0] >> 32) < A.pc;
-    cut = 1 + (int)draw_below(w[1], (uint32_t)(R - 1));
+    cross = xw0 < A.pc;
+    cut = 1 + (int)draw_below((u64)xw1 << 32, (uint32_t)(R - 1));
   }
   const int32_t *other = cross ? A.prio_in + (size_t)select_winner(A, partner) * L : mine;
   for (int k = lane; k < R; k += kWave) {
@@ -1289,12 +1309,10 @@ __device__ void breed_child_xy(const GaDev &A, const DInst &I, const XyTab &T, i
   }
   __asm__ volatile("" ::: "memory");
   if (cross) correct_lds(l.gy, R, (int32_t *)l.head, (int32_t *)l.zrec);
-  u64 w[4];
-  philox((u64)i, (u64)gen, (u64)A.event, (2ull << 32) | (u64)variant, A.seed, A.shop, w);
-  if ((uint32_t)(w[0] >> 32) < A.pm) {
+  if (mw0 < A.pm) {
     if (R >= 2) {
-      const int x = (int)draw_below(w[1], (uint32_t)R);
-      int y = (int)draw_below(w[2], (uint32_t)(R - 1));
+      const int x = (int)draw_below((u64)mw1 << 32, (uint32_t)R);
+      int y = (int)draw_below((u64)mw2 << 32, (uint32_t)(R - 1));
       y += y >= x;
       if (lane == 0) {
         const int gx = l.gy[x];
