@@ -422,7 +422,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     int2 *opp = l.op + vz;
     int2 o = *opp;
     uint32_t pqv = *recp;
-    int stage_work = 0;
+    int stage_work = vz;  // per lane: summed on the vector unit
     for (int k = 0; k < cnt; ++k) {
       opp += 1;
       recp += os;
@@ -469,11 +469,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const int end = t + p + rs;
       fr = ffs_writelane(end, mb, fr);
       opp[-1].x = PLAN ? end | (mb << 27) : end;
-      stage_work += cw;
+      stage_work = stage_work + cw;
       o = o_next;
       pqv = pq_next;
     }
-    work += (int64_t)stage_work + (power_ect ? 0 : 3 * os * cnt);
+    work += (int64_t)uni(stage_work) + (power_ect ? 0 : 3 * os * cnt);
     if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
     // Completion times back to the jobs; start and machine of every op.
