@@ -1044,6 +1044,12 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   int max_end = rs;
   int2 rec = R > 0 ? l.zrec[0] : make_int2(0, 0);
   if constexpr (NB > 0) {
+    uint64_t wsum;  // per lane: summed on the vector unit
+    {
+      int vz;
+      __asm__("v_mov_b32 %0, 0" : "=v"(vz));
+      wsum = (uint64_t)(uint32_t)vz;
+    }
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
       rec = l.zrec[min(z + 1, R - 1)];
@@ -1061,7 +1067,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
       rv0 = ffs_writelane(hi ? r0 : end, xl, rv0);
       if (NB > 1) rv1 = ffs_writelane(hi ? end : r1, xl, rv1);
       fmv = ffs_writelane(end, f, fmv);
-      work += (uint32_t)((t - t0) + 2 * p);  // non-negative
+      wsum += (uint32_t)((t - t0) + 2 * p);  // non-negative
       max_end = max(max_end, end);
       if (PLAN && lane == 0) {
         const int j = ld_const(I.active, x), s = f / I.om;
@@ -1069,6 +1075,8 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
         mach_out[(size_t)j * I.g + s] = f - s * I.om;
       }
     }
+    work = (int64_t)(((uint64_t)(uint32_t)uni((int)(uint32_t)(wsum >> 32)) << 32) |
+                     (uint32_t)uni((int)(uint32_t)wsum));
     if (lane < n) l.rdy[lane] = rv0;
     if (NB > 1 && kWave + lane < n) l.rdy[kWave + lane] = rv1;
   } else {
