@@ -897,9 +897,11 @@ struct XyTab {
 
 // LDS of one wave decoding an X/Y chromosome:
 //   gx   [R]      machine genes
-//   zrec [R]      ops in Z order: (x | (s * om + m) << 12, P|Q) for active job x
+//   zrec [R+1]    ops in Z order: (x | (s * om + m) << 12, P|Q) for active job x,
+//                 then a zero record the op loop reads one past the last
 //   rdy  [n]      completion of each active job's last placed stage
-//   fm   [g*om]   machine free times
+//   fm   [g*om]   machine free times (rdy and fm live in registers instead
+//                 when there are at most 128 jobs and 64 machine slots)
 //   then one region used twice: until Z is built, the priority genes gy [R]
 //   and head [R+1] (per priority value y: k | len << 24 when gene k starts a
 //   chain of len genes of one job whose running minimum of y is y, else 0);
@@ -1019,6 +1021,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     }
     base += __builtin_amdgcn_readlane(incl, kWave - 1);
   }
+  if (lane == 0) l.zrec[R] = make_int2(0, 0);  // spare record: the loop reads one past the last
   int rv0 = 0, rv1 = 0, fmv = 0;
   if constexpr (NB > 0) {
     if (lane < n) rv0 = ld_const(I.ready, ld_const(I.active, lane));
@@ -1045,14 +1048,16 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   int2 rec = R > 0 ? l.zrec[0] : make_int2(0, 0);
   if constexpr (NB > 0) {
     uint64_t wsum;  // per lane: summed on the vector unit
+    const int2 *zp;  // per lane too: records read with immediate offsets
     {
       int vz;
       __asm__("v_mov_b32 %0, 0" : "=v"(vz));
       wsum = (uint64_t)(uint32_t)vz;
+      zp = l.zrec + vz;
     }
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
-      rec = l.zrec[min(z + 1, R - 1)];
+      rec = *++zp;
       const int xl = x & (kWave - 1);
       // both registers read and written, the right one chosen: no branch
       const int r0 = __builtin_amdgcn_readlane(rv0, xl);
@@ -1086,7 +1091,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
       const int est = max(rs, uni(rdy_n)), fr = uni(fm_n);
-      rec = l.zrec[min(z + 1, R - 1)];
+      rec = l.zrec[z + 1];
       const int xfn = uni(rec.x), xn = xfn & 0xFFF, fn = xfn >> 12;
       rdy_n = l.rdy[xn];
       fm_n = l.fm[fn];
