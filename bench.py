@@ -448,8 +448,8 @@ def main():
                     help="first run a 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              f"described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the hot path is built and "
+              f"measured on one GPU; sharding it across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
