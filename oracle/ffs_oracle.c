@@ -216,15 +216,34 @@ static int place_op(decoder *d, int32_t j, int32_t s, int32_t machine,
       }
     }
   }
-  if (m == -2) {  /* power-aware: the earliest completion after each machine's push-right */
+  if (m == -2) {
+    /* power-aware: the earliest completion after each machine's push-right, ties
+     * to the lowest index. A push-right only delays, so max(est, free) + P
+     * bounds a machine's completion from below: the machine of least bound
+     * (ties to the lowest index) is pushed right first, then, in index order,
+     * only the machines whose (bound, index) is below the best (completion,
+     * index) found so far; the others cannot win. Work: 3 per machine for its
+     * bound, plus the examined slots and p of every machine pushed right. */
+    int32_t first = -1, first_lb = 0;
+    for (int32_t c = 0; c < o_s; ++c) {
+      if (Q_AT(in, j, s, c) > in->q_max) return ORC_E_INFEASIBLE;
+      const int32_t lb = MAX32(est, free_s[c]) + P_AT(in, j, s, c);
+      d->work += 3;
+      if (first < 0 || lb < first_lb) {
+        first = c;
+        first_lb = lb;
+      }
+    }
     int32_t best_end = 0;
     m = -1;
-    for (int32_t c = 0; c < o_s; ++c) {
+    for (int32_t k = -1; k < o_s; ++k) {
+      const int32_t c = k < 0 ? first : k;
+      if (k >= 0 && c == first) continue;
       const int32_t t0c = MAX32(est, free_s[c]), pc = P_AT(in, j, s, c);
-      if (Q_AT(in, j, s, c) > in->q_max) return ORC_E_INFEASIBLE;
+      if (m >= 0 && !(t0c + pc < best_end || (t0c + pc == best_end && c < m))) continue;
       const int32_t tc = push_right(d, t0c, pc, Q_AT(in, j, s, c));
-      d->work += 3 + (int64_t)(tc - t0c) + pc;
-      if (m < 0 || tc + pc < best_end) {
+      d->work += (int64_t)(tc - t0c) + pc;
+      if (m < 0 || tc + pc < best_end || (tc + pc == best_end && c < m)) {
         best_end = tc + pc;
         m = c;
       }

@@ -57,8 +57,11 @@ typedef struct {
  *   priority order.
  * ORC_RULE_POWER_ECT: the machine of earliest completion counting the power
  *   push-right on each machine (ties to the lowest index); by default the
- *   earliest completion ignoring power. Work per op then counts, for every
- *   machine, 3 + the slots its push-right examines + p, plus p updated.
+ *   earliest completion ignoring power. Machines whose completion ignoring
+ *   power cannot beat the best found so far are not pushed right (the
+ *   machine of least such bound goes first). Work per op then counts 3 per
+ *   machine, the examined slots + p of every machine pushed right, plus p
+ *   updated.
  * X/Y chromosomes fix both order and machine and ignore these bits. */
 #define ORC_RULE_FIFO 1
 #define ORC_RULE_POWER_ECT 2

@@ -436,22 +436,32 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
           (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
       int t = 0, cw = 0;
       if (power_ect) {
-        // FFS_RULE_POWER_ECT: each machine's push-right, the earliest completion
-        // after it (ties to the lowest index); every candidate's slots count as work
-        kmin = 0xFFFFFFFFu;
+        // FFS_RULE_POWER_ECT: the earliest completion after the machine's push-right
+        // (ties to the lowest index). The key above, (completion ignoring power) << 4
+        // | machine, bounds a machine's key after its push-right from below: the
+        // machine of least key goes first, then in index order only machines whose
+        // key is below the best so far. Work: 3 per machine, plus the examined
+        // slots and p of every machine pushed right.
         const int ox = uni(o.x);  // uniform: keeps this loop on the scalar unit
-        for (int m = 0; m < os; ++m) {
+        const int first = (int)(kmin & 15u);
+        uint32_t best = 0xFFFFFFFFu;
+        cw = 3 * os;
+        for (int k = -1; k < os; ++k) {
+          const int m = k < 0 ? first : k;
+          if (k >= 0 && m == first) continue;
+          if ((uint32_t)__builtin_amdgcn_readlane((int)key, m) >= best) continue;
           const uint32_t pqm = (uint32_t)__builtin_amdgcn_readlane((int)pqv, m);
           const int pm = (int)(pqm & 0xFFFFu);
           const int t0m = max(ox, __builtin_amdgcn_readlane(fr, m)) - rs;
           const int tm = prof.place(t0m, pm, (uint32_t)(I.q_max - (int)(pqm >> 16)));
-          cw += 3 + (tm - t0m) + pm;
+          cw += (tm - t0m) + pm;
           const uint32_t km = ((uint32_t)(tm + pm + rs) << 4) | (uint32_t)m;
-          if (km < kmin) {
-            kmin = km;
+          if (km < best) {
+            best = km;
             t = tm;
           }
         }
+        kmin = best;
       }
       const int mb = (int)(kmin & 15u);
       const uint32_t pq = (uint32_t)__builtin_amdgcn_readlane((int)pqv, mb);

@@ -55,13 +55,17 @@ def test_power_ect_takes_the_machine_of_earliest_feasible_completion():
     """Brute force on the decoded plans: replaying the ops in decode order, each op's
     machine gives the earliest completion over all machines of its stage, each
     placed at its first window that fits (ties to the lowest machine), and the op
-    starts exactly there."""
+    starts exactly there. The work count follows the pruned search: 3 per machine,
+    then the examined slots and p of the machine of least bound max(est, free) + p
+    and of every other machine whose (bound, index) is below the best (completion,
+    index) so far, then p updated."""
     for seed in range(6):
         inst = W.random_instance(seed, n_jobs=6, n_stages=2, machines=[2, 3], p_max=9,
                                  q_range=(1, 6), percent=45)
         rules = _with(inst, oracle.RULE_POWER_ECT)
         for prio in W.random_population(seed, 8, inst.n_active):
-            obj, start, mach, _ = oracle.decode(rules, prio, want_schedule=True)
+            obj, start, mach, work = oracle.decode(rules, prio, want_schedule=True)
+            want_work = 0
             validate.check_plan(inst.proc, inst.power, inst.release, inst.due, inst.n_machines,
                                 inst.q_max, inst.wt, start, mach)
             order = [j for _, j in sorted((-int(prio[k]), int(j)) for k, j in enumerate(inst.active))]
@@ -69,17 +73,32 @@ def test_power_ect_takes_the_machine_of_earliest_feasible_completion():
             done = {int(j): int(inst.release[j]) for j in inst.active}
             for s in range(inst.n_stages):
                 for j in order:
-                    best = None
-                    for m in range(int(inst.n_machines[s])):
+                    best, fits = None, {}
+                    o_s = int(inst.n_machines[s])
+                    for m in range(o_s):
                         p, q = int(inst.proc[j][s][m]), int(inst.power[j][s][m])
-                        t = _earliest_fit(prof, inst.q_max, max(done[j], free.get((s, m), 0)), p, q)
+                        t0 = max(done[j], free.get((s, m), 0))
+                        t = _earliest_fit(prof, inst.q_max, t0, p, q)
+                        fits[m] = (t0 + p, t - t0 + p)  # bound, examined slots + p
                         if best is None or t + p < best[0]:
                             best = (t + p, m, t)
                     assert mach[j][s] == best[1] and start[j][s] == best[2]
+                    first = min(range(o_s), key=lambda m: (fits[m][0], m))
+                    done_best = None
+                    want_work += 3 * o_s
+                    for m in [first] + [m for m in range(o_s) if m != first]:
+                        if done_best is not None and (fits[m][0], m) >= done_best:
+                            continue
+                        want_work += fits[m][1]
+                        end = fits[m][0] - int(inst.proc[j][s][m]) + fits[m][1]
+                        if done_best is None or (end, m) < done_best:
+                            done_best = (end, m)
                     p, q = int(inst.proc[j][s][best[1]]), int(inst.power[j][s][best[1]])
+                    want_work += p
                     for x in range(best[2], best[2] + p):
                         prof[x] = prof.get(x, 0) + q
                     free[(s, best[1])] = done[j] = best[2] + p
+            assert work == want_work
 
 
 def test_fifo_orders_each_stage_by_previous_completion():
