@@ -100,6 +100,10 @@ __device__ __forceinline__ uint32_t draw_below(u64 w, uint32_t n) {
 // v_writelane: a uniform value into one lane of a register (bound to the LLVM
 // intrinsic by name; hipcc has no builtin for it).
 extern "C" __device__ int ffs_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ u64 readlane64(u64 v, int lane) {
+  return (u64)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane) << 32 |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+}
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Lane mask of a predicate across the wave.
@@ -377,6 +381,18 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     // with FFS_RULE_FIFO by the completion of the previous stage, then rank),
     // plus a spare record so the op loop can prefetch one past the last.
     int cnt = 0;
+    // FFS_RULE_FIFO with at most 128 jobs: keys (completion << 32 | rank) of the
+    // stage's jobs in two registers, all ones for jobs not at this stage; a
+    // job's place is the number of keys below its own, counted against keys
+    // broadcast one lane at a time.
+    const bool fifo_reg = fifo && n <= 2 * kWave;
+    u64 fk0 = ~0ull, fk1 = ~0ull;
+    if (fifo_reg) {
+      if (lane < n && (l.jobs[lane] >> 24) <= s)
+        fk0 = (u64)(uint32_t)l.rdy[lane] << 32 | (uint32_t)lane;
+      if (kWave + lane < n && (l.jobs[kWave + lane] >> 24) <= s)
+        fk1 = (u64)(uint32_t)l.rdy[kWave + lane] << 32 | (uint32_t)(kWave + lane);
+    }
     for (int b = 0; b < n; b += kWave) {
       const int x = b + lane;
       const int jf = x < n ? l.jobs[x] : (127 << 24);
@@ -384,7 +400,14 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const u64 mk = ballot64(live);
       if (live) {
         int k = cnt + __popcll(mk & below);
-        if (fifo) {
+        if (fifo_reg) {
+          const u64 kx = b == 0 ? fk0 : fk1;
+          k = 0;
+          for (int y = 0; y < min(n, kWave); ++y)
+            k += readlane64(fk0, y) < kx;
+          for (int y = kWave; y < n; ++y)
+            k += readlane64(fk1, y - kWave) < kx;
+        } else if (fifo) {
           const int cx = l.rdy[x];
           k = 0;
           for (int y = 0; y < n; ++y) {

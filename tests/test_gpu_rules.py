@@ -53,6 +53,31 @@ def test_decode_rules_match_oracle(rules):
                     assert (st[i] == s2).all() and (mc[i] == m2).all()
 
 
+@pytest.mark.parametrize("n_jobs", [60, 100, 150])
+def test_fifo_order_for_each_job_count_layout(n_jobs):
+    """FIFO stage order with the keys in one register (up to 64 jobs), in two
+    (65-128) and in LDS (more), at event 0 and after an arrival, against the oracle."""
+    torch, ffsga = _ffs()
+    base = W.random_instance(23, n_jobs=n_jobs, n_stages=3, machines=[2, 3, 2], p_max=30, percent=55)
+    st, mc = oracle.decode(base, W.random_population(1, 1, base.n_active)[0], want_schedule=True)[1:3]
+    arr = W.random_arrival(6, base, 40, 9, p_max=30)
+    later = W.Instance.from_fields(oracle.reschedule(base, st, mc, arr.rs, arr.proc, arr.power,
+                                                     arr.release, arr.due))
+    for name, b in (("event 0", base), ("event 1", later)):
+        inst = dataclasses.replace(b, decode_rules=1)
+        _say("FIFO", n_jobs, "jobs", name, "n_active", inst.n_active)
+        d = ffsga.DeviceInstance.from_host(inst)
+        prio = W.random_population(5, 64, inst.n_active)
+        want, wwork = oracle.decode_pop(inst, prio, n_threads=8, want_work=True)
+        got = ffsga.ffs_decode(d, torch.from_numpy(prio).cuda(), want_schedule=True, want_work=True)
+        assert (got["obj"].cpu().numpy() == want).all()
+        assert (got["work"].cpu().numpy() == wwork).all()
+        st2, mc2 = got["start"].cpu().numpy(), got["mach"].cpu().numpy()
+        for i in (0, 63):
+            _, s3, m3, _ = oracle.decode(inst, prio[i], want_schedule=True)
+            assert (st2[i] == s3).all() and (mc2[i] == m3).all()
+
+
 def _state(ga):
     v = ga.view()
     return {k: t.cpu().numpy() for k, t in v.items() if k != "work"}
