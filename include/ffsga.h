@@ -81,8 +81,11 @@ typedef struct {
  *   first, ties by priority; by default every stage takes the priority order.
  * FFS_RULE_POWER_ECT: each op takes the machine of earliest completion after
  *   that machine's power push-right (ties to the lowest index); by default the
- *   earliest completion ignoring power. Its work count per op is, over every
- *   machine, 3 + the slots its push-right examines + p, plus p updated. */
+ *   earliest completion ignoring power. A push-right only delays, so a machine
+ *   whose completion ignoring power is not below the best found so far is not
+ *   pushed right (the machine of least such bound goes first). Its work count
+ *   per op is 3 per machine, plus the examined slots + p of every machine
+ *   pushed right, plus p updated. */
 #define FFS_RULE_FIFO 1
 #define FFS_RULE_POWER_ECT 2
 
