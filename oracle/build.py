@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libffsoracle.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "ffs_oracle.c")
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared",
+    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared",
            "-o", tmp, src]
     if verbose:
         print(" ".join(cmd), flush=True)
