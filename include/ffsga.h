@@ -119,6 +119,30 @@ int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64
                int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
                void *workspace, size_t workspace_bytes, void *stream);
 
+/* Bytes of the library-owned device buffer behind ffs_decode_noalloc (one copy
+ * per GPU, held until the process ends). */
+#define FFS_DECODE_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. ffs_decode
+ * with its workspace taken from a static device buffer of
+ * FFS_DECODE_SCRATCH_BYTES bytes that the library holds on each GPU, instead
+ * of from the caller. Arguments, outputs, kernels and results are those of
+ * ffs_decode without workspace/workspace_bytes; the caller still owns prio,
+ * obj, start, mach and work. The call allocates nothing (no hipMalloc, no
+ * allocating library routine) and the buffer's header is cleared by a kernel,
+ * not a memset. Every call on one GPU shares that GPU's buffer, which keeps
+ * the last call's contents: calls that overlap on one GPU (on different
+ * streams or host threads) race and must be ordered by the caller.
+ * A chromosome the kernels reject gets obj = -1; the device-side flags that
+ * ffs_status reads for a caller's workspace stay in the shared buffer.
+ * Errors: as ffs_decode; FFS_E_WORKSPACE when ffs_decode_workspace_size(inst,
+ * pop, lds_slots) exceeds FFS_DECODE_SCRATCH_BYTES (nothing is launched);
+ * FFS_E_DEVICE when the buffer's device address cannot be obtained. */
+int ffs_decode_noalloc(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
+                       int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+                       void *stream);
+
 /* Decode pop X/Y chromosomes (Section 4.3, eqs. (10)-(12), Algorithms 1-2):
  * the paper's own encoding, a target machine and a priority per operation.
  * genes: device [pop][2 * n_ops]. Genes cover the n_ops unfrozen ops only

@@ -40,6 +40,10 @@ typedef __attribute__((address_space(4))) const int32_t c_i32;
 typedef __attribute__((address_space(4))) const uint32_t c_u32;
 typedef __attribute__((address_space(4))) const int64_t c_i64;
 
+// Workspace of ffs_decode_noalloc: one copy per GPU, held until the process
+// ends, shared by every such call on that GPU.
+static __device__ __align__(256) uint8_t scratch[FFS_DECODE_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int kWave = 64;
@@ -1870,6 +1874,13 @@ __global__ __launch_bounds__(256) void batch_advance_kernel(BatchArgs B) {
 // ---------------------------------------------------------------------------
 // Instance preparation: packing, checks, horizon bound, rescheduling.
 // ---------------------------------------------------------------------------
+// Zero a workspace header with one wave (a kernel, not a memset, so the
+// no-allocation decode holds kernels only).
+__global__ __launch_bounds__(64) void clear_header_kernel(Header *h) {
+  static_assert(kHeaderBytes == 4 * kWave, "one word per lane");
+  ((int32_t *)h)[threadIdx.x] = 0;
+}
+
 __global__ void pack_kernel(const int32_t *proc, const int32_t *power, uint32_t *pq, int rows,
                             int om, int omp) {
   const size_t total = (size_t)rows * omp;
@@ -2727,6 +2738,65 @@ int batch_init_launch(const ffs_batch *b, const BatchArgs &B, int slot, const Ba
   return FFS_OK;
 }
 
+// Body of ffs_decode and ffs_decode_noalloc: checks, header cleared (by a
+// memset, or by a kernel for callers that may capture the call in a graph),
+// instance packed, population decoded.
+int decode_job_vectors(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
+                       int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+                       void *workspace, size_t workspace_bytes, hipStream_t s,
+                       bool clear_by_kernel) {
+  int rc = check_host(inst);
+  if (rc) return rc;
+  if (inst->horizon < 1 || pop < 0 || (pop > 0 && (!obj || (!prio && inst->n_active > 0))) ||
+      ((start == nullptr) != (mach == nullptr)))
+    return FFS_E_INVAL;
+  if (pop == 0) return FFS_OK;
+  const int cap = resolve_cap(inst, lds_slots);
+  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
+    return FFS_E_UNSUPPORTED;
+  if (!workspace || workspace_bytes < decode_layout(nullptr, inst, pop, cap).total)
+    return FFS_E_WORKSPACE;
+  DecodeLayout L = decode_layout(workspace, inst, pop, cap);
+  if (clear_by_kernel) {
+    if (launch(-1, clear_header_kernel, dim3(1), dim3(kWave), 0, s, L.hdr) != hipSuccess)
+      return FFS_E_DEVICE;
+  } else if ((rc = clear_header(L.hdr, s))) {
+    return rc;
+  }
+  if ((rc = pack(inst, L.pq, s))) return rc;
+  switch (omp_of(inst->o_max)) {
+    case 4:
+      set_lds_limits<4>();
+      return run_decode<4>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+    case 8:
+      set_lds_limits<8>();
+      return run_decode<8>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+    default:
+      set_lds_limits<16>();
+      return run_decode<16>(inst, prio, pop, obj, start, mach, work, cap, L, s);
+  }
+}
+
+// Address of this GPU's copy of the no-allocation decode's scratch buffer,
+// looked up once per device (each GPU holds the array at its own address; the
+// array's name in host code is only a stand-in for the symbol).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FFS_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FFS_E_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FFS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2780,32 +2850,22 @@ size_t ffs_decode_workspace_size(const ffs_instance *inst, int32_t pop, int32_t 
 int ffs_decode(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
                int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots, void *workspace,
                size_t workspace_bytes, void *stream) {
+  return decode_job_vectors(inst, prio, pop, obj, start, mach, work, lds_slots, workspace,
+                            workspace_bytes, (hipStream_t)stream, false);
+}
+
+int ffs_decode_noalloc(const ffs_instance *inst, const int32_t *prio, int32_t pop, int64_t *obj,
+                       int32_t *start, int32_t *mach, int64_t *work, int32_t lds_slots,
+                       void *stream) {
   int rc = check_host(inst);
   if (rc) return rc;
-  if (inst->horizon < 1 || pop < 0 || (pop > 0 && (!obj || (!prio && inst->n_active > 0))) ||
-      ((start == nullptr) != (mach == nullptr)))
-    return FFS_E_INVAL;
-  if (pop == 0) return FFS_OK;
-  const int cap = resolve_cap(inst, lds_slots);
-  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
-    return FFS_E_UNSUPPORTED;
-  if (!workspace || workspace_bytes < ffs_decode_workspace_size(inst, pop, lds_slots))
+  if (inst->horizon < 1 || pop < 0) return FFS_E_INVAL;
+  if (pop > 0 && ffs_decode_workspace_size(inst, pop, lds_slots) > (size_t)FFS_DECODE_SCRATCH_BYTES)
     return FFS_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  DecodeLayout L = decode_layout(workspace, inst, pop, cap);
-  if ((rc = clear_header(L.hdr, s))) return rc;
-  if ((rc = pack(inst, L.pq, s))) return rc;
-  switch (omp_of(inst->o_max)) {
-    case 4:
-      set_lds_limits<4>();
-      return run_decode<4>(inst, prio, pop, obj, start, mach, work, cap, L, s);
-    case 8:
-      set_lds_limits<8>();
-      return run_decode<8>(inst, prio, pop, obj, start, mach, work, cap, L, s);
-    default:
-      set_lds_limits<16>();
-      return run_decode<16>(inst, prio, pop, obj, start, mach, work, cap, L, s);
-  }
+  void *ws = nullptr;
+  if ((rc = static_scratch(&ws))) return rc;
+  return decode_job_vectors(inst, prio, pop, obj, start, mach, work, lds_slots, ws,
+                            FFS_DECODE_SCRATCH_BYTES, (hipStream_t)stream, true);
 }
 
 int ffs_decode_xy(const ffs_instance *inst, const int32_t *genes, int32_t pop, int64_t *obj,

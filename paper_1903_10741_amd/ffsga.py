@@ -24,6 +24,7 @@ FFS_E_WORKSPACE = -3
 FFS_E_DEVICE = -4
 FFS_E_UNSUPPORTED = -5
 FFS_PREPARE_WORKSPACE = 256
+FFS_DECODE_SCRATCH_BYTES = 16 << 20
 
 TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
 TIMING_BATCH, TIMING_SCREENED = 4, 5
@@ -85,6 +86,8 @@ _lib.ffs_decode.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp,
                             ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
 _lib.ffs_decode_xy.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
                                ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+_lib.ffs_decode_noalloc.argtypes = [_P(FfsInstance), _vp, ctypes.c_int32, _vp, _vp, _vp, _vp,
+                                    ctypes.c_int32, _vp]
 _lib.ffs_status.argtypes = [_vp, _vp]
 _lib.ffs_ga_workspace_size.argtypes = [_P(FfsInstance), _P(FfsGaParams)]
 _lib.ffs_ga_workspace_size.restype = ctypes.c_size_t
@@ -104,7 +107,7 @@ _lib.ffs_strerror.argtypes = [ctypes.c_int]
 _lib.ffs_strerror.restype = ctypes.c_char_p
 _lib.ffs_build_id.argtypes = []
 _lib.ffs_build_id.restype = ctypes.c_char_p
-for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
+for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_noalloc", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
            "reschedule", "ffs_timing_enable", "ffs_timing_every", "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -211,11 +214,7 @@ class DeviceInstance:
         return out
 
 
-def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
-               want_schedule: bool = False, want_work: bool = False, workspace=None,
-               xy: bool = False):
-    """Decode prio [pop, n_active] (int32, cuda), or with xy=True X/Y chromosomes
-    [pop, 2 * n_ops] (ffs_decode_xy). Returns obj (int64 [pop]) or a dict."""
+def _decode_outputs(dinst, prio, want_schedule, want_work):
     s = dinst.s
     dev = dinst.t["proc"].device
     prio = prio.to(device=dev, dtype=torch.int32).contiguous()
@@ -227,6 +226,17 @@ def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
         mach = torch.full((pop, s.n_jobs, s.n_stages), -1, dtype=torch.int32, device=dev)
     if want_work:
         work = torch.empty(pop, dtype=torch.int64, device=dev)
+    return prio, pop, obj, start, mach, work
+
+
+def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
+               want_schedule: bool = False, want_work: bool = False, workspace=None,
+               xy: bool = False):
+    """Decode prio [pop, n_active] (int32, cuda), or with xy=True X/Y chromosomes
+    [pop, 2 * n_ops] (ffs_decode_xy). Returns obj (int64 [pop]) or a dict."""
+    s = dinst.s
+    dev = dinst.t["proc"].device
+    prio, pop, obj, start, mach, work = _decode_outputs(dinst, prio, want_schedule, want_work)
     need = _lib.ffs_decode_workspace_size(ctypes.byref(s), pop, int(lds_slots))
     if need == 0:
         raise FfsError(FFS_E_INVAL, "ffs_decode_workspace_size")
@@ -237,6 +247,20 @@ def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
               _dptr(work), int(lds_slots), _dptr(ws), ws.numel(), _stream()),
            "ffs_decode_xy" if xy else "ffs_decode")
     _check(_lib.ffs_status(_dptr(ws), _stream()), "ffs_decode (device status)")
+    if want_schedule or want_work:
+        return {"obj": obj, "start": start, "mach": mach, "work": work}
+    return obj
+
+
+def ffs_decode_noalloc(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
+                       want_schedule: bool = False, want_work: bool = False):
+    """ffs_decode on the library's own per-GPU scratch buffer (no workspace argument).
+    Output tensors are allocated here, as for ffs_decode; the call itself allocates nothing."""
+    s = dinst.s
+    prio, pop, obj, start, mach, work = _decode_outputs(dinst, prio, want_schedule, want_work)
+    _check(_lib.ffs_decode_noalloc(ctypes.byref(s), _dptr(prio), pop, _dptr(obj), _dptr(start),
+                                   _dptr(mach), _dptr(work), int(lds_slots), _stream()),
+           "ffs_decode_noalloc")
     if want_schedule or want_work:
         return {"obj": obj, "start": start, "mach": mach, "work": work}
     return obj
@@ -392,7 +416,8 @@ def timing_read(family):
 def exported_symbols():
     """Names declared in include/ffsga.h that the loaded library exports."""
     names = []
-    for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_decode_xy",
+    for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_decode_noalloc",
+                 "ffs_decode_xy",
                  "ffs_status",
                  "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
                  "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
