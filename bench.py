@@ -1,13 +1,16 @@
 """Benchmark: exact chromosome decodes per second of the whole EDFFS hot path on one GPU.
 
-One step = one complete predictive-reactive run of the paper-shaped workload
-(50 jobs, 5 stages, 3 unrelated machines per stage, 5 arrival events; the
-island GA with 32 islands of 8x16 = 4096 individuals, 500 generations per
-event, 2 best migrating every 10 generations): for each of the 6 events the
-GA (init + 500 generations of selection, crossover, mutation, decode,
-replacement, migration), the decode of the executed plan, and the
-rescheduling at the next arrival. Inputs are synthetic and seeded, resident
-on the GPU before the timed region starts.
+Default workload: large-200x10x4-6 (200 jobs, 10 stages, 4-6 unrelated
+machines per stage, 10 arrival events of 10-30 jobs; the island GA with 512
+islands of 8x16 = 65536 individuals, 200 generations per event, 2 best
+migrating every 10 generations). One step = one event: the GA (init + 200
+generations of selection, crossover, mutation, decode, replacement,
+migration), the decode of the executed plan, and the rescheduling at the next
+arrival; consecutive steps go through the 11 events in order and start again
+at event 0. Inputs are synthetic and seeded, resident on the GPU before the
+timed region starts. The paper-shaped workload (50 jobs, 5 stages, 3
+machines, 6 events of 4096 individuals x 500 generations, one step = all 6
+events) is measured beside it and reported under "paper_shaped".
 
 Prints one JSON line. `roofline` reports the GA generation kernel (breed +
 decode, the dominant kernel) against the chip's int32 VALU issue rate, with
@@ -42,18 +45,15 @@ def cpu_baseline(wl):
     t1 = time.perf_counter()
     oracle.ga_run(wl.initial, wl.ga, wl.seed, wl.shop, 0, 4, n_threads=1)
     dt1 = time.perf_counter() - t1
-    model = ""
-    try:
-        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
-                     if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    model = cpu_model()
     return {"value": decodes / dt, "unit": "decodes/s", "cores": threads, "kind": "oracle",
             "sample": f"one full step: {len(out)} events x (1 + {wl.generations}) generations x "
                       f"{wl.ga.pop} individuals + plan decodes ({decodes} decodes, {dt:.1f} s)",
             "single_thread": {"value": 5 * wl.ga.pop / dt1, "unit": "decodes/s", "cores": 1,
-                              "sample": f"event 0, generation 0 + 4 generations ({5 * wl.ga.pop} "
-                                        f"decodes, {dt1:.1f} s)"},
+                              "sample": f"event 0 only (50 jobs; later events have up to 100 and "
+                                        f"decode slower, so this rate is optimistic): generation "
+                                        f"0 + 4 generations ({5 * wl.ga.pop} decodes, "
+                                        f"{dt1:.1f} s)"},
             "nproc": os.cpu_count(), "cpu_model": model,
             "best_obj_per_event": [int(e["best_obj"]) for e in out]}
 
@@ -142,64 +142,165 @@ def bench_batch(args):
     return out
 
 
+def oracle_rate_large(wl, gens=10):
+    """The CPU oracle on event 0 of the large workload: init + `gens` generations of
+    the whole population (OpenMP over the population, all host threads), and one
+    thread on a bounded sample of random priority vectors."""
+    import oracle
+    from paper_1903_10741_amd import workloads as W
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    oracle.ga_run(wl.initial, wl.ga, wl.seed, wl.shop, 0, gens, n_threads=threads)
+    dt = time.perf_counter() - t0
+    decodes = (1 + gens) * wl.ga.pop
+    sample = W.random_population(wl.seed + 1, 1024, wl.initial.n_active)
+    t1 = time.perf_counter()
+    oracle.decode_pop(wl.initial, sample, n_threads=1)
+    dt1 = time.perf_counter() - t1
+    rate = decodes / dt
+    full = (1 + len(wl.arrivals)) * ((1 + wl.generations) * wl.ga.pop + 1)
+    return {"value": rate, "unit": "decodes/s", "cores": threads, "kind": "oracle",
+            "sample": f"event 0 only (200 jobs; later events have up to 385 and decode slower, so "
+                      f"this rate is optimistic for the whole run): init + {gens} generations of "
+                      f"{wl.ga.pop} individuals ({decodes} decodes, {dt:.1f} s)",
+            "extrapolated_full_run_s": full / rate,
+            "extrapolated_note": f"{full} decodes of the 11 events at the event-0 rate",
+            "single_thread": {"value": len(sample) / dt1, "unit": "decodes/s", "cores": 1,
+                              "sample": f"event 0, {len(sample)} random priority vectors "
+                                        f"({dt1:.1f} s)"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        return next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                    if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return ""
+
+
+def profile_figures(kname, workload):
+    """HBM bytes and VALU issue per launch from the rocprofv3 counter runs committed
+    under profiles/, used only when they were taken on this very build."""
+    from paper_1903_10741_amd import ffsga
+    tpath = os.path.join(ROOT, "profiles", f"{kname}_{workload}.traffic.json")
+    if not os.path.exists(tpath):
+        return None, None
+    t = json.load(open(tpath))
+    if t.get("build_id") != ffsga.ffs_build_id():
+        return None, None
+    return (t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"],
+            t.get("valu_issue_tlops"))
+
+
 def bench_large(args):
-    """Large decode throughput: event 0 of large-200x10x4-6 (200 jobs, 10 stages, 4-6
-    unrelated machines, population 65536 = 512 islands x 8x16) for 200 generations in
-    the batched launch, one slot; the autotuner times one wave per child against one
-    wave per island (and the on-chip profile sizes) and the step runs the faster."""
+    """The large workload end to end: large-200x10x4-6 (200 jobs, 10 stages, 4-6
+    unrelated machines per stage, 10 arrival events of 10-30 jobs; 512 islands x
+    8x16 = 65536 individuals, 200 generations per event). One step = one event:
+    the GA (init + 200 generations), the executed plan's decode and the
+    rescheduling at the next arrival; steps go through the 11 events in order and
+    start again at event 0 (whose instance stays resident). The on-chip profile
+    of each event is sized from its generation 0 (FFS_LDS_AUTO). Before the timed
+    region the autotuner times one wave per chromosome against one wave per
+    island on event 0; the GA runs in the faster schedule."""
     import torch
     from paper_1903_10741_amd import autotune, ffsga
     from paper_1903_10741_amd import workloads as W
+    from paper_1903_10741_amd.run import EventLoop
     wl = W.config3(args.seed)
-    gens = args.generations or wl.generations
-    inst = wl.initial
-    dev = [ffsga.DeviceInstance.from_host(inst)]
+    if args.generations is not None:
+        wl.generations = args.generations
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    cands = []
-    for lds in (8192, 16384):
-        for sched, blocks in ((ffsga.FFS_SCHEDULE_CHROMOSOME, 8 * n_cu),
-                              (ffsga.FFS_SCHEDULE_CHROMOSOME, 16 * n_cu),
-                              (ffsga.FFS_SCHEDULE_ISLAND, 2 * n_cu),
-                              (ffsga.FFS_SCHEDULE_ISLAND, 4 * n_cu)):
-            cands.append(autotune.Candidate(sched, lds, blocks, True))
-    tune = autotune.tune(dev, [inst], wl.ga, candidates=cands, generations=2, log=progress)
-    b = ffsga.Batch(autotune.batch_config([inst], wl.ga, dev[0].horizon, tune.best))
-
-    def one_step():
-        b.set(0, dev[0], args.seed, 0, 0)
-        b.step(gens)
-    for _ in range(args.warmup):
-        one_step()
-    b.status()
+    tune = None
+    if not args.no_autotune:
+        d0 = ffsga.DeviceInstance.from_host(wl.initial)
+        cands = [autotune.Candidate(ffsga.FFS_SCHEDULE_CHROMOSOME, 8192, 8 * n_cu, True),
+                 autotune.Candidate(ffsga.FFS_SCHEDULE_ISLAND, 8192, 2 * n_cu, True)]
+        tune = autotune.tune([d0], [wl.initial], wl.ga, candidates=cands, generations=2,
+                             log=progress)
+        if tune.best.schedule != ffsga.FFS_SCHEDULE_CHROMOSOME:
+            raise SystemExit("the autotuner picked one wave per island for the large workload; "
+                             "this benchmark runs the event loop on ga_step (one wave per "
+                             "chromosome) and would not measure the tuned schedule")
+        del d0
+    loop = EventLoop(wl, lds_slots=ffsga.FFS_LDS_AUTO)
+    for k in range(args.warmup):
+        loop.run_event()
+        progress(f"large warm-up step {k + 1} done")
+    torch.cuda.synchronize()
+    ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION], every=8)
+    per_event, events = [], []
+    decodes = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        one_step()
-        b.stream.synchronize()
-        progress(f"large step {k + 1} done")
+        ts = time.perf_counter()
+        ev = loop.run_event()     # ends synchronised (plan decode status, rescheduling)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        decodes += ev.decodes
+        events.append(ev)
+        per_event.append({"event": ev.event, "n_active": ev.n_active, "lds_slots": ev.lds_slots,
+                          "s": dt, "decodes_per_s": ev.decodes / dt})
+        progress(f"large step {k + 1}: event {ev.event}, {ev.n_active} jobs, "
+                 f"{ev.lds_slots} on-chip slots, {dt:.2f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    b.status()
-    decodes = wl.ga.pop * (1 + gens)
-    best = {s: min(r["us_per_generation"] for r in tune.table if r["schedule"] == s)
-            for s in (ffsga.FFS_SCHEDULE_CHROMOSOME, ffsga.FFS_SCHEDULE_ISLAND)}
-    out = common(args, "exact chromosome decodes/sec", decodes * args.steps / elapsed, "decodes/s",
-                 elapsed * 1e3 / args.steps, "int32", {
-                     "workload": f"large-200x10x4-6 event 0: 200 jobs, 10 stages, 4-6 unrelated "
-                                 f"machines, 512 islands x 8x16 = 65536, {gens} generations",
-                     "decodes_per_step": decodes, "autotuned": tune.best.__dict__,
-                     "us_per_generation_wave_per_child": best[ffsga.FFS_SCHEDULE_CHROMOSOME],
-                     "us_per_generation_wave_per_island": best[ffsga.FFS_SCHEDULE_ISLAND],
-                     "tuning_table": tune.table})
+    gen_ms, gen_launches = ffsga.timing_read(ffsga.TIMING_GENERATION)
+    ffsga.timing_enable(False)
+    work = sum(int(ev.work.item()) for ev in events)
+    ga_decodes = sum(ev.decodes - 1 for ev in events)
+    work_per_decode = work / max(ga_decodes, 1)
+    avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
+    achieved = work_per_decode * wl.ga.pop / avg_launch_s / 1e12
+    traffic, valu_issue = profile_figures("ga_generation_kernel", "large-200x10x4-6")
+    best = {}
+    for ev in events:
+        best.setdefault(ev.event, int(ev.best_obj.item()))
+    config = {
+        "workload": "large-200x10x4-6: 200 jobs, 10 stages, 4-6 unrelated machines per stage, "
+                    "10 arrival events of 10-30 jobs; 512 islands x 8x16 = 65536, 200 "
+                    "generations per event; one step = one event (GA init + 200 generations + "
+                    "executed-plan decode + rescheduling), steps cycling through the 11 events",
+        "encoding": "job priority vector",
+        "decodes_per_step_mean": decodes / args.steps,
+        "events_timed": [ev.event for ev in events],
+        "per_event": per_event,
+        "best_obj_per_event": [best[e] for e in sorted(best)],
+        "on_chip_slots": "sized per event from generation 0's longest schedule (FFS_LDS_AUTO)",
+    }
+    if tune is not None:
+        config["autotuned"] = {"pick": tune.best.__dict__, "table": tune.table}
+    out = common(args, "exact chromosome decodes/sec", decodes / elapsed, "decodes/s",
+                 elapsed * 1e3 / args.steps, "int32", config)
+    out["roofline"] = {
+        "bound": "alu",
+        "kernel": "ga_generation_kernel (selection, crossover, mutation, decode)",
+        "achieved": achieved,
+        "peak": VALU_INT32_PEAK_TOPS,
+        "unit": "TOP/s int32",
+        "frac": achieved / VALU_INT32_PEAK_TOPS,
+        "traffic": traffic,
+        "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
+        "work_per_decode": work_per_decode,
+        "decodes_per_launch": wl.ga.pop,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "timed_launches": gen_launches,
+        "timed_every": 8,
+        "build_id": ffsga.ffs_build_id(),
+    }
     return out
 
 
 def bench_serve(args):
-    """Rescheduling requests from 512 shops arriving Poisson at 200/s: each request
-    is one arrival event (U{5..10} new jobs) of a shop whose first plan exists,
-    rescheduled and then 100 generations of population 1024, continuously
-    batched; latency and throughput. The first plans are made beforehand through
-    the same path and not counted."""
+    """Rescheduling requests from 512 shops arriving Poisson: each request is one
+    arrival event (U{5..10} new jobs) of a shop whose first plan exists, rescheduled
+    and then 100 generations of population 1024, continuously batched; latency and
+    throughput. The first plans are made beforehand through the same path and not
+    counted. With --rates r1,r2,...: a latency-vs-load sweep, the shops split into
+    one group per rate (both arrivals of each shop of group k offered at rate k),
+    every rate served by the same primed service one after the other."""
+    import numpy as np
     import torch
     from paper_1903_10741_amd import autotune, ffsga
     from paper_1903_10741_amd import workloads as W
@@ -218,16 +319,33 @@ def bench_serve(args):
     progress("first plans")
     first = srv.prime()
     progress(f"first plans done in {first['wall_s']:.1f} s; serving starts")
-    sched = poisson_schedule(args.seed, args.rate, [n_arrivals] * len(shops))
-    torch.cuda.synchronize()
-    m = srv.run(sched, log=progress)
-    out = common(args, "exact chromosome decodes/sec", m["decodes_per_s"], "decodes/s",
-                 m["wall_s"] * 1e3, "int32", {
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else [args.rate]
+    groups = np.array_split(np.arange(len(shops)), len(rates))
+    curve = []
+    for k, (rate, grp) in enumerate(zip(rates, groups)):
+        n_events = [n_arrivals if s in set(grp.tolist()) else 0 for s in range(len(shops))]
+        sched = poisson_schedule(args.seed + k, rate, n_events)
+        srv.reset_metrics()
+        torch.cuda.synchronize()
+        m = srv.run(sched, log=progress)
+        progress(f"rate {rate}/s: {m['done']} served, p50 {m['latency_p50_s']:.2f} s, "
+                 f"p99 {m['latency_p99_s']:.2f} s, {m['decodes_per_s']:.3g} decodes/s")
+        curve.append({"offered_per_s": rate, "shops": len(grp), **m})
+    need = 1.03e5 * 200   # decodes per request x the workload's 200 requests/s
+    last = curve[-1]
+    out = common(args, "exact chromosome decodes/sec", last["decodes_per_s"], "decodes/s",
+                 last["wall_s"] * 1e3, "int32", {
                      "workload": f"serving: {len(shops)} shops, {n_arrivals} arrival requests each "
-                                 f"(U{{5..10}} jobs), Poisson {args.rate}/s, {gens} generations x "
-                                 f"pop 1024 per request",
+                                 f"(U{{5..10}} jobs), {gens} generations x pop 1024 per request, "
+                                 f"Poisson arrivals at {', '.join(f'{r:g}' for r in rates)}/s" +
+                                 (f" (shops split into {len(rates)} groups, one per rate)"
+                                  if len(rates) > 1 else ""),
                      "first_plans_s": first["wall_s"],
-                     **{k: v for k, v in m.items()}})
+                     "value_at": f"offered {rates[-1]:g} requests/s",
+                     "decodes_per_s_needed_at_200_per_s": need,
+                     "capacity_gap": need / max(max(c["decodes_per_s"] for c in curve), 1.0),
+                     "autotuned": tune.best.__dict__,
+                     "curve": curve})
     out["steps"] = 1
     out["warmup"] = 0
     return out
@@ -416,8 +534,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="paper",
-                    choices=["paper", "batch", "serve", "surrogate", "large"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "paper", "batch", "serve", "surrogate"],
+                    help="large (default): the large-200x10x4-6 event loop, one event per step, "
+                         "with the paper-shaped workload measured beside it")
     ap.add_argument("--lds-slots", type=int, default=0)
     ap.add_argument("--rules", type=int, default=0, choices=[0, 1, 2, 3],
                     help="paper workload: job-vector decode variants, bit 0 FIFO stage order, "
@@ -426,11 +546,16 @@ def main():
                     help="paper workload: one priority per job (default) or the paper's X/Y "
                          "machine and priority matrices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="large workload: skip the paper-shaped measurement beside it")
+    ap.add_argument("--paper-steps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--generations", type=int, default=None,
                     help="override generations per event (profiling runs only)")
     ap.add_argument("--shops", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rates", default=None,
+                    help="serve: comma-separated offered request rates for a latency-vs-load sweep")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--race-seeds", type=int, default=10)
@@ -443,7 +568,8 @@ def main():
                          "of each seeded run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch: the usual tuned configuration (8192 profile slots in 3 classes, "
-                         "8 blocks per CU, one wave per child, graph) without tuning")
+                         "8 blocks per CU, one wave per child, graph) without tuning; large: "
+                         "skip the schedule comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -454,6 +580,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    copy_calibration(args)
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)), flush=True)
         return
@@ -463,13 +590,48 @@ def main():
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args)), flush=True)
         return
-    if args.workload == "large":
-        print(json.dumps(bench_large(args)), flush=True)
+    if args.workload == "paper":
+        out = bench_paper(args, args.steps, args.warmup)
+        if not args.no_cpu_baseline:
+            from paper_1903_10741_amd import workloads as W
+            out["cpu_baseline"] = cpu_baseline(W.config2(args.seed))
+        print(json.dumps(out), flush=True)
         return
-    bench_paper(args)
+    out = bench_large(args)
+    if not args.no_paper:
+        progress("paper-shaped workload")
+        paper = bench_paper(args, args.paper_steps, 1)
+        if not args.no_cpu_baseline:
+            from paper_1903_10741_amd import workloads as W
+            paper["cpu_baseline"] = cpu_baseline(W.config2(args.seed))
+        out["paper_shaped"] = {k: paper[k] for k in ("value", "unit", "steps", "warmup",
+                                                     "ms_per_step", "config", "roofline",
+                                                     "cpu_baseline") if k in paper}
+    if not args.no_cpu_baseline:
+        from paper_1903_10741_amd import workloads as W
+        progress("CPU oracle (large workload, event 0)")
+        out["cpu_baseline"] = oracle_rate_large(W.config3(args.seed))
+    print(json.dumps(out), flush=True)
 
 
-def bench_paper(args):
+def copy_calibration(args):
+    """A 256 MiB device-to-device copy: the reference the HBM byte counters of a
+    profiling run are scaled by."""
+    if not args.copy_calibration:
+        return
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def bench_paper(args, steps, warmup):
+    """The paper-shaped workload end to end: one step = every event of paper-50x5x3
+    (the GA's init + 500 generations, the executed plan's decode and the
+    rescheduling, for each of the 6 events)."""
+    import dataclasses
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
@@ -479,31 +641,22 @@ def bench_paper(args):
     if args.generations is not None:
         wl.generations = args.generations
     xy = args.encoding == "xy"
-    import dataclasses
     if xy:
         wl.ga = dataclasses.replace(wl.ga, encoding=1)
     if args.rules:
         wl.initial = dataclasses.replace(wl.initial, decode_rules=args.rules)
-    if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         run_workload(wl, lds_slots=args.lds_slots)
     torch.cuda.synchronize()
 
     # events on the generation kernel only, one launch in 8 (spread evenly over
     # the timed steps): the other launches carry no markers
     ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION], every=8)
-    work = 0
     decodes = 0
-    best = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         res = run_workload(wl, lds_slots=args.lds_slots, sync_results=False)
         decodes += res.decodes
     torch.cuda.synchronize()
@@ -511,66 +664,44 @@ def bench_paper(args):
     gen_ms, gen_launches = ffsga.timing_read(ffsga.TIMING_GENERATION)
     ffsga.timing_enable(False)
     best = [int(e.best_obj.item()) for e in res.events]
+    # algorithmic work of the generation kernel, counted by the decoder (the last
+    # timed step's own counters: every step computes the same)
+    work_per_decode = sum(int(e.work.item()) for e in res.events) / max(res.ga_decodes, 1)
 
-    # algorithmic work of the generation kernel, counted by the decoder
-    work_res = run_workload(wl, lds_slots=args.lds_slots, sync_results=True, keep_work=True)
-    work_per_decode = work_res.work / max(work_res.ga_decodes, 1)
-
-    value = decodes / elapsed
-    traffic = None
-    valu_issue = None
     kname = "ga_generation_xy_kernel" if xy else "ga_generation_kernel"
-    tpath = os.path.join(ROOT, "profiles", f"{kname}_paper-50x5x3.traffic.json")
-    if os.path.exists(tpath):
-        t = json.load(open(tpath))
-        if t.get("build_id") == ffsga.ffs_build_id():  # counters of this very build only
-            traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
-            valu_issue = t.get("valu_issue_tlops")
+    traffic, valu_issue = profile_figures(kname, "paper-50x5x3")
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
-    decodes_per_launch = wl.ga.pop
-    achieved = work_per_decode * decodes_per_launch / avg_launch_s / 1e12
-    out = {
-        "metric": "exact chromosome decodes/sec",
-        "value": value,
-        "unit": "decodes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (seeded generator, paper-shaped)",
-        "config": {
-            "workload": "paper-shaped plain GA: 50 jobs, 5 stages, 3 unrelated machines, "
-                        "5 arrival events, 32 islands x 8x16 = 4096, 500 generations/event" +
-                        (", X/Y chromosome (machine and priority per operation)" if xy else ""),
-            "encoding": "xy" if xy else "job priority vector",
-            "decode_rules": args.rules,
-            "decodes_per_step": decodes // args.steps,
-            "events": 1 + len(wl.arrivals),
-            "best_obj_per_event": best,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": f"{kname} (selection, crossover, mutation, decode)",
-            "achieved": achieved,
-            "peak": VALU_INT32_PEAK_TOPS,
-            "unit": "TOP/s int32",
-            "frac": achieved / VALU_INT32_PEAK_TOPS,
-            "traffic": traffic,
-            "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
-            "work_per_decode": work_per_decode,
-            "avg_launch_us": avg_launch_s * 1e6,
-            "timed_launches": gen_launches,
-            "timed_every": 8,
-            "build_id": ffsga.ffs_build_id(),
-        },
+    achieved = work_per_decode * wl.ga.pop / avg_launch_s / 1e12
+    out = common(args, "exact chromosome decodes/sec", decodes / elapsed, "decodes/s",
+                 elapsed * 1e3 / steps, "int32", {
+                     "workload": "paper-shaped plain GA: 50 jobs, 5 stages, 3 unrelated machines, "
+                                 "5 arrival events, 32 islands x 8x16 = 4096, 500 "
+                                 "generations/event; one step = all 6 events" +
+                                 (", X/Y chromosome (machine and priority per operation)"
+                                  if xy else ""),
+                     "encoding": "xy" if xy else "job priority vector",
+                     "decode_rules": args.rules,
+                     "decodes_per_step": decodes // steps,
+                     "events": 1 + len(wl.arrivals),
+                     "best_obj_per_event": best})
+    out["steps"], out["warmup"] = steps, warmup
+    out["roofline"] = {
+        "bound": "alu",
+        "kernel": f"{kname} (selection, crossover, mutation, decode)",
+        "achieved": achieved,
+        "peak": VALU_INT32_PEAK_TOPS,
+        "unit": "TOP/s int32",
+        "frac": achieved / VALU_INT32_PEAK_TOPS,
+        "traffic": traffic,
+        "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
+        "work_per_decode": work_per_decode,
+        "decodes_per_launch": wl.ga.pop,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "timed_launches": gen_launches,
+        "timed_every": 8,
+        "build_id": ffsga.ffs_build_id(),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -88,8 +88,9 @@ int sg_score(const ffs_surrogate *model, const float *table, int32_t n_genes, co
 
 /* Training targets: t[i] = (ln obj[i] - mean) / sd over each group of `group`
  * consecutive entries (one population; the last group may be shorter), mean
- * and population standard deviation in float64 summed in index order, the
- * result rounded to float32; a group with sd = 0 gets 0. obj device int64
+ * and population standard deviation in float64 summed in a fixed order (256
+ * runs of consecutive entries, each in index order, then a fixed pairwise
+ * tree), the result rounded to float32; a group with sd = 0 gets 0. obj device int64
  * [count] (> 0), target device float32 [count]. workspace: device, at least
  * FFS_PREPARE_WORKSPACE bytes; an objective <= 0 is reported by the next
  * ffs_status(workspace) as FFS_E_INVAL. */

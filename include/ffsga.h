@@ -176,12 +176,24 @@ typedef struct {
   int32_t islands, rows, cols;
   uint32_t pc, pm;
   int32_t mig_interval, mig_k;
-  int32_t lds_slots;                /* on-chip profile slots per decode, 0 = default */
+  int32_t lds_slots;                /* on-chip profile slots per decode, 0 = default (4096);
+                                       FFS_LDS_AUTO: sized by ga_init from generation 0 */
   int32_t encoding;                 /* 0: one priority per active job (n_genes = n_active);
                                        1: the paper's X/Y matrices (n_genes = 2 * n_ops, see
                                        ffs_decode_xy). The batched GA and ga_step_screened
                                        take encoding 0 only (else FFS_E_UNSUPPORTED). */
 } ffs_ga_params;
+
+/* ffs_ga_params.lds_slots = FFS_LDS_AUTO (job-priority vectors only; encoding 1
+ * gets FFS_E_UNSUPPORTED): ga_init decodes generation 0 with as many on-chip
+ * slots as one workgroup's LDS holds (at most 32768, no more than the horizon
+ * needs), records the longest schedule (end - RS) and keeps 5/4 of it plus 64
+ * slots (a multiple of 64) on chip for every later generation, so long
+ * schedules stay on chip and short ones leave LDS for more waves per compute
+ * unit. ga_init then synchronises its stream once and ffs_ga.lds_slots holds
+ * the chosen slots. A later decode that outgrows them is redone off chip as
+ * usual: results never depend on the choice. */
+#define FFS_LDS_AUTO (-1)
 
 /* GA state. Filled by ga_init; the caller owns the struct and the workspace.
  * The device pointers point into the workspace. ga_step must be given the

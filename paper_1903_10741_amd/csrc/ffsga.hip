@@ -30,6 +30,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ffs_surrogate.h"
@@ -68,6 +69,8 @@ struct Header {
   int64_t frozen_tardiness;
   int32_t frozen_cmax, n_running, n_active, n_ops;  // n_ops: unfrozen ops (ffs_prepare)
   unsigned long long work;  // algorithmic work of every decode of a GA
+  int32_t span_max;     // longest schedule (end - RS) of a sizing decode (FFS_LDS_AUTO)
+  int32_t pad1;
 };
 static_assert(sizeof(Header) <= kHeaderBytes, "header");
 
@@ -109,6 +112,11 @@ __device__ __forceinline__ u64 readlane64(u64 v, int lane) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
 }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+// A wave-uniform unsigned sum read out to the scalar side.
+__device__ __forceinline__ u64 uniform_sum(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ u64 uniform_sum(u64 v) { return readlane64(v, 0); }
 
 // Lane mask of a predicate across the wave.
 __device__ __forceinline__ u64 ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -266,7 +274,8 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //   rdy   [n]        by rank: completion of the job's last placed stage
 //   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20);
 //                    a placed op's earliest start is overwritten by its end time
-//   rec   [n+1][o_s] the current stage's packed P | Q << 16 rows, one word per machine
+//   rec   [2][kRing] packed P | Q << 16 rows of the stage's ops, one word per machine,
+//                    staged from the packed table kWave / o_s ops at a time, double buffered
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
 // gene is free once the ranks are built.
@@ -277,12 +286,16 @@ struct Lds {
   uint8_t *prof;
 };
 
-__host__ __device__ inline size_t lds_bytes(int n, int cap, int maxm) {
-  return 3 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) +
-         align_up((size_t)4 * maxm * (n + 1), 16) + (cap > 0 ? align_up(cap, 16) + kWave : 0);
+// Words of one row-ring buffer: a chunk of kWave / o_s ops of o_s words each,
+// plus the record the op loop prefetches one past the chunk (read, never used).
+constexpr int kRing = kWave + 16;
+
+__host__ __device__ inline size_t lds_bytes(int n, int cap) {
+  return 3 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) + 8 * kRing +
+         (cap > 0 ? align_up(cap, 16) + kWave : 0);
 }
 
-__device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n, int maxm) {
+__device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   Lds l;
   const size_t a = align_up((size_t)4 * n + 4, 16);
   l.gene = (int32_t *)smem;
@@ -290,7 +303,7 @@ __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n, int maxm) {
   l.rdy = (int32_t *)(smem + 2 * a);
   l.op = (int2 *)(smem + 3 * a);
   l.rec = (uint32_t *)(smem + 3 * a + align_up((size_t)8 * n + 8, 16));
-  l.prof = (uint8_t *)l.rec + align_up((size_t)4 * maxm * (n + 1), 16);
+  l.prof = (uint8_t *)l.rec + 8 * kRing;
   return l;
 }
 
@@ -421,26 +434,29 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         }
         const int j = jf & 0xFFFFFF;
         l.op[k] = make_int2(max(rs, l.rdy[x]), (int)((uint32_t)j | ((uint32_t)x << 20)));
-        // the packed row is padded to MAXM words: load it whole, keep o_s words
-        const uint4 *row = (const uint4 *)(I.pq + ((size_t)j * I.g + s) * I.omp);
-        uint4 w[MAXM / 4];
-#pragma unroll
-        for (int c = 0; c < MAXM / 4; ++c) w[c] = row[c];
-#pragma unroll
-        for (int m = 0; m < MAXM; ++m) {
-          const uint32_t word = m % 4 == 0 ? w[m / 4].x
-                                : m % 4 == 1 ? w[m / 4].y
-                                : m % 4 == 2 ? w[m / 4].z
-                                             : w[m / 4].w;
-          if (m < os) l.rec[k * os + m] = word;
-        }
       }
       cnt += __popcll(mk);
     }
-    if (lane < os) l.rec[cnt * os + lane] = 0;
     if (lane == 0) l.op[cnt] = make_int2(0, 0);
     __asm__ volatile("" ::: "memory");
-    const uint32_t *recp = l.rec + min(lane, os - 1);
+    // The ops' packed P|Q rows come from the packed table chunk by chunk: lane
+    // lk * o_s + lm holds machine lm of op lk of a chunk of kWave / o_s ops.
+    // The rows of chunk c + 1 are loaded while chunk c runs and stored into the
+    // other ring buffer when it ends, so the loads' latency stays hidden and
+    // LDS holds two chunks instead of the whole stage.
+    const int C = kWave / os, lk = lane / os, lm = lane - lk * os;
+    const uint32_t *pq_stage = I.pq + (size_t)s * I.omp + lm;
+    const size_t pq_job = (size_t)I.g * I.omp;
+    auto row_word = [&](int k) -> uint32_t {
+      if (lk >= C || k >= cnt) return 0u;
+      const int j = l.op[k].y & 0xFFFFF;
+      return pq_stage[(size_t)j * pq_job];
+    };
+    {
+      const uint32_t w0 = row_word(lk);
+      if (lk < C) l.rec[lane] = w0;
+    }
+    __asm__ volatile("" ::: "memory");
     // The record pointer as a per-lane value (the asm hides that the zero is
     // uniform): records are then read and written through one vector address
     // with immediate offsets instead of a scalar address moved in every op.
@@ -448,9 +464,22 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     __asm__("v_mov_b32 %0, 0" : "=v"(vz));
     int2 *opp = l.op + vz;
     int2 o = *opp;
-    uint32_t pqv = *recp;
-    int stage_work = vz;  // per lane: summed on the vector unit
-    for (int k = 0; k < cnt; ++k) {
+    // The stage's work sum, per lane (summed on the vector unit). Default rules:
+    // the push-right intervals [t0, t) of one machine's ops are disjoint and lie
+    // within the span after RS (< 2^27 slots), so over at most 16 machines they
+    // add up to at most 2^31, and the 2p terms to at most 2 * 4096 * 65535 < 2^29:
+    // unsigned 32 bits hold the sum. The power-aware rule pushes several machines
+    // right per op, over the same slots again for later ops: 64 bits.
+    using StageWork = typename std::conditional<RULES, u64, uint32_t>::type;
+    StageWork stage_work = (StageWork)(uint32_t)vz;
+    for (int base = 0, c = 0; base < cnt; base += C, ++c) {
+      const uint32_t *ring = l.rec + (c & 1) * kRing;
+      uint32_t *next_ring = l.rec + (1 - (c & 1)) * kRing;
+      const uint32_t next_w = row_word(base + C + lk);  // in flight during this chunk
+      const uint32_t *recp = ring + min(lane, os - 1);
+      uint32_t pqv = *recp;
+      const int k_end = min(base + C, cnt);
+    for (int k = base; k < k_end; ++k) {
       opp += 1;
       recp += os;
       const int2 o_next = *opp;
@@ -461,7 +490,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const uint32_t key = ((uint32_t)(mx + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
       uint32_t kmin =
           (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
-      int t = 0, cw = 0;
+      int t = 0;
+      StageWork cw = 0;
       if (power_ect) {
         // FFS_RULE_POWER_ECT: the earliest completion after the machine's push-right
         // (ties to the lowest index). The key above, (completion ignoring power) << 4
@@ -481,7 +511,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
           const int pm = (int)(pqm & 0xFFFFu);
           const int t0m = max(ox, __builtin_amdgcn_readlane(fr, m)) - rs;
           const int tm = prof.place(t0m, pm, (uint32_t)(I.q_max - (int)(pqm >> 16)));
-          cw += (tm - t0m) + pm;
+          cw += (StageWork)((tm - t0m) + pm);
           const uint32_t km = ((uint32_t)(tm + pm + rs) << 4) | (uint32_t)m;
           if (km < best) {
             best = km;
@@ -498,9 +528,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // threshold only makes every slot pass, so the push-right still ends.
         const int t0 = __builtin_amdgcn_readlane(t0v, mb);
         t = prof.place(t0, p, (uint32_t)(I.q_max - q));
-        cw = (t - t0) + 2 * p;
+        cw = (StageWork)((t - t0) + 2 * p);
       } else {
-        cw += p;
+        cw += (StageWork)p;
       }
       prof.commit(t, p, q);
       const int end = t + p + rs;
@@ -510,7 +540,10 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       o = o_next;
       pqv = pq_next;
     }
-    work += (int64_t)uni(stage_work) + (power_ect ? 0 : 3 * os * cnt);
+      if (lk < C) next_ring[lane] = next_w;
+      __asm__ volatile("" ::: "memory");
+    }
+    work += (int64_t)uniform_sum(stage_work) + (power_ect ? 0 : 3 * os * cnt);
     if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
     // Completion times back to the jobs; start and machine of every op.
@@ -522,7 +555,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       l.rdy[jx >> 20] = end;
       if (PLAN) {
         const size_t at = (size_t)(jx & 0xFFFFFu) * I.g + s;
-        start_out[at] = end - (int)(l.rec[k * os + mb] & 0xFFFFu);
+        const uint32_t pqb = I.pq[((size_t)(jx & 0xFFFFFu) * I.g + s) * I.omp + mb];
+        start_out[at] = end - (int)(pqb & 0xFFFFu);
         mach_out[at] = mb;
       }
     }
@@ -584,7 +618,7 @@ __global__ __launch_bounds__(64) void decode_kernel(DInst I, const int32_t *__re
                                                     int cap) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int i = blockIdx.x;
-  Lds l = carve_lds(smem, I.n, MAXM);
+  Lds l = carve_lds(smem, I.n);
   const int32_t *src = prio + (size_t)i * I.n;
   for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];
   __asm__ volatile("" ::: "memory");
@@ -608,7 +642,7 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
                                                       const int32_t *ovf_list, uint8_t *gprof,
                                                       size_t gstride) {
   extern __shared__ __align__(16) uint8_t smem[];
-  Lds l = carve_lds(smem, I.n, MAXM);
+  Lds l = carve_lds(smem, I.n);
   const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   GlobalProfile prof{gprof + gstride * blockIdx.x, offchip_cap(I.horizon)};
   for (int e = blockIdx.x; e < count; e += gridDim.x) {
@@ -832,10 +866,12 @@ __device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
 // off-chip redo, which the wave does itself when it has a profile of its own.
 template <int MAXM>
 __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
-                                  int tag) {
+                                  int tag, int32_t *span = nullptr) {
   int64_t work = 0;
   int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
-                                    nullptr);
+                                    nullptr, span);
+  // a schedule longer than the on-chip slots: at least cap + 1 of them
+  if (st == kDecOverflow && span && __lane_id() == 0) atomicMax(span, cap + 1);
   if (st == kDecOverflow && A.redo_prof) {
     const int32_t *src = A.prio_out + (size_t)i * I.n;
     for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];  // this lane's own stores
@@ -904,18 +940,20 @@ __global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = A.rows * A.cols;
   const int i = slot_of_block(blockIdx.x, K, A.islands);
-  const Lds l = carve_lds(smem, I.n, MAXM);
+  const Lds l = carve_lds(smem, I.n);
   breed_child(A, I.n, i, gen, l);
   decode_and_record<MAXM>(I, A, i, cap, l, i);
 }
 
+// Generation 0. span: null, or where the longest schedule is recorded
+// (ga_init sizes the on-chip profile of later generations from it).
 template <int MAXM>
-__global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap) {
+__global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap, int32_t *span) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int i = blockIdx.x;
-  const Lds l = carve_lds(smem, I.n, MAXM);
+  const Lds l = carve_lds(smem, I.n);
   init_child(A, I.n, i, l);
-  decode_and_record<MAXM>(I, A, i, cap, l, i);
+  decode_and_record<MAXM>(I, A, i, cap, l, i, span);
 }
 
 // ---------------------------------------------------------------------------
@@ -1474,7 +1512,7 @@ __global__ __launch_bounds__(64) void ga_screened_kernel(DInst I, GaDev A, int g
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = A.rows * A.cols, pop = K * A.islands;
   const int i = slot_of_block(blockIdx.x, K, A.islands);
-  const Lds l = carve_lds(smem, I.n, MAXM);
+  const Lds l = carve_lds(smem, I.n);
   const float b3 = theta[FFS_SG_PARAMS - 1];
   int best = 0;
   float best_s = 0.f;
@@ -1776,7 +1814,7 @@ __global__ __launch_bounds__(64) void batch_generation_kernel(BatchArgs B, int c
     if (!S.active || S.cls != cls) continue;
     const int gen = S.gen + 1;
     const GaDev A = slot_ga(S, B, gen);
-    const Lds l = carve_lds(smem, S.I.n, MAXM);
+    const Lds l = carve_lds(smem, S.I.n);
     const GlobalProfile gp{gp_mem, offchip_cap(S.I.horizon)};
     if (ISLAND) {
       const int isl = item % per_slot;
@@ -1802,7 +1840,7 @@ __global__ __launch_bounds__(64) void batch_init_kernel(BatchArgs B, int d) {
   GaDev A0 = A;
   A0.prio_out = S.prio[0];
   A0.obj_out = S.obj[0];
-  const Lds l = carve_lds(smem, S.I.n, MAXM);
+  const Lds l = carve_lds(smem, S.I.n);
   const GlobalProfile gp{B.gprof + B.gstride * blockIdx.x, offchip_cap(S.I.horizon)};
   for (int i = blockIdx.x; i < B.pop; i += gridDim.x) {
     init_child(A0, S.I.n, i, l);
@@ -2256,12 +2294,12 @@ int run_decode(const ffs_instance *in, const int32_t *prio, int32_t pop, int64_t
                int32_t *start, int32_t *mach, int64_t *work, int cap, const DecodeLayout &L,
                hipStream_t stream) {
   const DInst d = make_dinst(in, L.pq);
-  const size_t shmem = lds_bytes(in->n_active, cap, MAXM);
+  const size_t shmem = lds_bytes(in->n_active, cap);
   hipError_t e = launch(0, decode_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, prio, obj,
                         work, start, mach, L.hdr, L.ovf_list, cap);
   if (e != hipSuccess) return FFS_E_DEVICE;
   if (cap < in->horizon) {
-    e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave), lds_bytes(in->n_active, 0, MAXM),
+    e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave), lds_bytes(in->n_active, 0),
                stream, d, prio, obj, work, start, mach, L.hdr, (const int32_t *)L.ovf_list, L.gprof,
                L.gstride);
     if (e != hipSuccess) return FFS_E_DEVICE;
@@ -2386,6 +2424,25 @@ GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int
   return L;
 }
 
+// The on-chip slots a GA workspace layout is computed with: with FFS_LDS_AUTO
+// the slots are only known after generation 0, so the layout always holds the
+// off-chip profiles.
+int layout_cap(const ffs_ga_params *p, int cap) { return p->lds_slots == FFS_LDS_AUTO ? 0 : cap; }
+
+// On-chip slots of the sizing decode of FFS_LDS_AUTO: as many as one
+// workgroup's LDS holds next to the chromosome's arrays, at most kProbeSlots
+// (longer schedules then keep that many, the rest of each decode going off
+// chip) and no more than the horizon needs.
+constexpr int64_t kProbeSlots = 32768;
+int probe_cap(const ffs_instance *in) {
+  const int64_t h = (int64_t)align_up((size_t)in->horizon, 64);
+  const int64_t room = (int64_t)max_lds_bytes() - (int64_t)lds_bytes(in->n_active, 0) - kWave;
+  int64_t cap = room / 64 * 64;
+  if (cap > kProbeSlots) cap = kProbeSlots;
+  if (cap > h) cap = h;
+  return (int)(cap < 64 ? 64 : cap);
+}
+
 int check_ga_params(const ffs_ga_params *p) {
   if (!p || p->islands < 1 || p->rows < 1 || p->cols < 1 || p->mig_k < 0 || p->mig_interval < 0)
     return FFS_E_INVAL;
@@ -2436,7 +2493,7 @@ int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hip
                (const int32_t *)L.ovf_list, L.gprof, L.gstride);
   else
     e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
-               lds_bytes(in->n_active, 0, MAXM), stream, d, (const int32_t *)L.prio[buf],
+               lds_bytes(in->n_active, 0), stream, d, (const int32_t *)L.prio[buf],
                L.obj[buf], (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, L.hdr,
                (const int32_t *)L.ovf_list, L.gprof, L.gstride);
   return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
@@ -2450,7 +2507,8 @@ int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t
 }
 
 template <int MAXM>
-int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStream_t stream) {
+int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStream_t stream,
+                 bool auto_cap) {
   const DInst d = make_dinst(in, L.pq);
   GaDev A = make_gadev(ga, L, 1);  // generation 0 is written to buffer 0
   const int pop = ga->pop, cap = ga->lds_slots, n = ga->n_genes;
@@ -2463,8 +2521,9 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
                lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap), stream, d,
                XyTab{L.xyop, L.xyg0, in->n_ops}, A, cap) != hipSuccess)
       return FFS_E_DEVICE;
-  } else if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap, MAXM),
-                    stream, d, A, cap) != hipSuccess) {
+  } else if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap),
+                    stream, d, A, cap, auto_cap ? &L.hdr->span_max : (int32_t *)nullptr) !=
+             hipSuccess) {
     return FFS_E_DEVICE;
   }
   rc = ga_overflow<MAXM>(in, L, 0, cap, stream, xy);
@@ -2473,6 +2532,14 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
              (const int32_t *)L.prio[0], (const int64_t *)L.obj[0], L.elite, L.elite_obj, K,
              n) != hipSuccess)
     return FFS_E_DEVICE;
+  if (auto_cap) {
+    // later generations keep 5/4 of generation 0's longest schedule + 64 slots on chip
+    Header host;
+    if ((rc = read_header(L.hdr, &host, stream))) return rc;
+    const int64_t span = host.span_max;
+    const int64_t want = (int64_t)align_up((size_t)(span + span / 4 + 64), 64);
+    ga->lds_slots = (int32_t)(want < cap ? want : cap);
+  }
   return FFS_OK;
 }
 
@@ -2487,14 +2554,14 @@ struct Screen {
 template <int MAXM>
 int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t stream,
                  const Screen *scr = nullptr) {
-  GaLayout L = ga_layout(ga->workspace, in, &ga->params, ga->lds_slots);
+  GaLayout L = ga_layout(ga->workspace, in, &ga->params, layout_cap(&ga->params, ga->lds_slots));
   const DInst d = make_dinst(in, L.pq);
   const int pop = ga->pop, cap = ga->lds_slots, n = ga->n_genes;
   const int K = ga->params.rows * ga->params.cols;
   const bool xy = ga->params.encoding == 1;
   const XyTab T{L.xyop, L.xyg0, in->n_ops};
   const size_t shmem = xy ? lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap)
-                          : lds_bytes(in->n_active, cap, MAXM);
+                          : lds_bytes(in->n_active, cap);
   for (int32_t k = 0; k < n_gen; ++k) {
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
@@ -2675,7 +2742,7 @@ int batch_generation_launches(const ffs_batch *b, const BatchArgs &B, hipStream_
   hipError_t e = hipSuccess;
   // one launch per profile size class, each with that class's LDS
   for (int c = 0; c < n_cls && e == hipSuccess; ++c) {
-    const size_t shmem = lds_bytes(p.max_genes, b->lds_slots >> (n_cls - 1 - c), MAXM);
+    const size_t shmem = lds_bytes(p.max_genes, b->lds_slots >> (n_cls - 1 - c));
     if (p.schedule == FFS_SCHEDULE_ISLAND)
       e = launch(timed ? 4 : -1, batch_generation_kernel<MAXM, true>, dim3(b->blocks), dim3(kWave),
                  shmem, s, B, c);
@@ -2722,7 +2789,7 @@ int batch_init_launch(const ffs_batch *b, const BatchArgs &B, int slot, const Ba
                       hipStream_t s) {
   set_batch_lds_limits<MAXM>();
   const ffs_batch_params &p = b->params;
-  const size_t shmem = lds_bytes(p.max_genes, b->lds_slots, MAXM);
+  const size_t shmem = lds_bytes(p.max_genes, b->lds_slots);
   const int grid = b->pop < b->blocks ? b->pop : b->blocks;
   if (launch(-1, batch_init_kernel<MAXM>, dim3(grid), dim3(kWave), shmem, s, B, slot) != hipSuccess ||
       launch(-1, batch_class_kernel, dim3(1), dim3(kWave), 0, s, B, slot, batch_classes(&p),
@@ -2752,7 +2819,7 @@ int decode_job_vectors(const ffs_instance *inst, const int32_t *prio, int32_t po
     return FFS_E_INVAL;
   if (pop == 0) return FFS_OK;
   const int cap = resolve_cap(inst, lds_slots);
-  if (lds_bytes(inst->n_active, cap, omp_of(inst->o_max)) > (size_t)max_lds_bytes())
+  if (lds_bytes(inst->n_active, cap) > (size_t)max_lds_bytes())
     return FFS_E_UNSUPPORTED;
   if (!workspace || workspace_bytes < decode_layout(nullptr, inst, pop, cap).total)
     return FFS_E_WORKSPACE;
@@ -2918,7 +2985,7 @@ int ffs_status(void *workspace, void *stream) {
 size_t ffs_ga_workspace_size(const ffs_instance *inst, const ffs_ga_params *params) {
   if (check_host(inst) || check_ga_params(params) || inst->horizon < 1) return 0;
   const int cap = resolve_cap(inst, params->lds_slots);
-  return ga_layout(nullptr, inst, params, cap).total;
+  return ga_layout(nullptr, inst, params, layout_cap(params, cap)).total;
 }
 
 int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, uint64_t seed,
@@ -2927,10 +2994,12 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   if (rc) return rc;
   if (!ga || inst->horizon < 1) return FFS_E_INVAL;
   if ((rc = check_ga_params(params))) return rc;
-  const int cap = resolve_cap(inst, params->lds_slots);
+  const bool auto_cap = params->lds_slots == FFS_LDS_AUTO;
+  if (auto_cap && params->encoding != 0) return FFS_E_UNSUPPORTED;
+  const int cap = auto_cap ? probe_cap(inst) : resolve_cap(inst, params->lds_slots);
   const size_t lds = params->encoding == 1
                          ? lds_bytes_xy(inst->n_active, inst->n_ops, inst->n_stages, inst->o_max, cap)
-                         : lds_bytes(inst->n_active, cap, omp_of(inst->o_max));
+                         : lds_bytes(inst->n_active, cap);
   if (lds > (size_t)max_lds_bytes()) return FFS_E_UNSUPPORTED;
   const size_t need = ffs_ga_workspace_size(inst, params);
   if (!workspace || workspace_bytes < need) return FFS_E_WORKSPACE;
@@ -2949,7 +3018,7 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   ga->n_jobs = inst->n_jobs;
   ga->horizon = inst->horizon;
   hipStream_t s = (hipStream_t)stream;
-  GaLayout L = ga_layout(workspace, inst, params, cap);
+  GaLayout L = ga_layout(workspace, inst, params, layout_cap(params, cap));
   for (int k = 0; k < 2; ++k) {
     ga->prio[k] = L.prio[k];
     ga->obj[k] = L.obj[k];
@@ -2971,13 +3040,13 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   switch (omp_of(inst->o_max)) {
     case 4:
       set_lds_limits<4>();
-      return ga_init_impl<4>(ga, inst, L, s);
+      return ga_init_impl<4>(ga, inst, L, s, auto_cap);
     case 8:
       set_lds_limits<8>();
-      return ga_init_impl<8>(ga, inst, L, s);
+      return ga_init_impl<8>(ga, inst, L, s, auto_cap);
     default:
       set_lds_limits<16>();
-      return ga_init_impl<16>(ga, inst, L, s);
+      return ga_init_impl<16>(ga, inst, L, s, auto_cap);
   }
 }
 
@@ -3126,7 +3195,7 @@ int ga_batch_create(ffs_batch *b, const ffs_batch_params *params, void *workspac
   b->omp = omp_of(params->o_max);
   b->workspace = workspace;
   b->workspace_bytes = workspace_bytes;
-  if (lds_bytes(params->max_genes, b->lds_slots, b->omp) > (size_t)max_lds_bytes())
+  if (lds_bytes(params->max_genes, b->lds_slots) > (size_t)max_lds_bytes())
     return FFS_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   BatchLayout L = batch_layout(workspace, params);

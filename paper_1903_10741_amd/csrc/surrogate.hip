@@ -269,35 +269,48 @@ __global__ __launch_bounds__(256) void validate_kernel(const int32_t *prio, cons
 // ---------------------------------------------------------------------------
 // Training targets: ln obj standardised within each group of `group`
 // consecutive chromosomes (one population), mean and population standard
-// deviation in float64, summed in index order; a constant group gets 0.
-// One block per group.
+// deviation in float64; a constant group gets 0. One block of 256 threads per
+// group: thread t sums its run of consecutive entries [g0 + t*c, g0 + (t+1)*c)
+// in index order, c = ceil(group / 256), and the 256 partial sums are added by
+// a fixed pairwise tree, so every run gives the same bits.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum_fixed(double v, double *buf) {
+  const int t = threadIdx.x;
+  buf[t] = v;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) buf[t] += buf[t + w];
+    __syncthreads();
+  }
+  const double out = buf[0];
+  __syncthreads();
+  return out;
+}
+
 __global__ __launch_bounds__(256) void targets_kernel(const int64_t *obj, int count, int group,
                                                      float *target, int32_t *status) {
-  __shared__ double stat[2];
+  __shared__ double buf[256];
   const int g0 = blockIdx.x * group;
   const int g1 = g0 + group < count ? g0 + group : count;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    bool bad = false;
-    for (int i = g0; i < g1; ++i) {
-      bad |= obj[i] <= 0;
-      s += log((double)(obj[i] > 0 ? obj[i] : 1));
-    }
-    const double mean = s / (double)(g1 - g0);
-    double v = 0.0;
-    for (int i = g0; i < g1; ++i) {
-      const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - mean;
-      v += d * d;
-    }
-    stat[0] = mean;
-    stat[1] = sqrt(v / (double)(g1 - g0));
-    if (bad) atomicOr(status, 1);
+  const int c = (g1 - g0 + 255) / 256;
+  const int a = min(g0 + (int)threadIdx.x * c, g1), b = min(a + c, g1);
+  double s = 0.0;
+  bool bad = false;
+  for (int i = a; i < b; ++i) {
+    bad |= obj[i] <= 0;
+    s += log((double)(obj[i] > 0 ? obj[i] : 1));
   }
-  __syncthreads();
+  if (bad) atomicOr(status, 1);
+  const double mean = block_sum_fixed(s, buf) / (double)(g1 - g0);
+  double v = 0.0;
+  for (int i = a; i < b; ++i) {
+    const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - mean;
+    v += d * d;
+  }
+  const double sd = sqrt(block_sum_fixed(v, buf) / (double)(g1 - g0));
   for (int i = g0 + threadIdx.x; i < g1; i += blockDim.x) {
-    const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - stat[0];
-    target[i] = stat[1] > 0.0 ? (float)(d / stat[1]) : 0.f;
+    const double d = log((double)(obj[i] > 0 ? obj[i] : 1)) - mean;
+    target[i] = sd > 0.0 ? (float)(d / sd) : 0.f;
   }
 }
 

@@ -25,6 +25,7 @@ FFS_E_DEVICE = -4
 FFS_E_UNSUPPORTED = -5
 FFS_PREPARE_WORKSPACE = 256
 FFS_DECODE_SCRATCH_BYTES = 16 << 20
+FFS_LDS_AUTO = -1
 
 TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
 TIMING_BATCH, TIMING_SCREENED = 4, 5
@@ -214,14 +215,22 @@ class DeviceInstance:
         return out
 
 
-def _decode_outputs(dinst, prio, want_schedule, want_work):
+def _decode_outputs(dinst, prio, want_schedule, want_work, start=None, mach=None):
     s = dinst.s
     dev = dinst.t["proc"].device
     prio = prio.to(device=dev, dtype=torch.int32).contiguous()
     pop = int(prio.shape[0]) if prio.dim() == 2 else 1
     obj = torch.empty(pop, dtype=torch.int64, device=dev)
-    start = mach = work = None
-    if want_schedule:
+    work = None
+    if start is not None or mach is not None:
+        # caller-owned plan arrays: decoded ops are written, frozen entries kept
+        shape = (pop * s.n_jobs * s.n_stages,)
+        for t in (start, mach):
+            if (t is None or t.dtype != torch.int32 or not t.is_contiguous() or t.device != dev
+                    or tuple(t.reshape(-1).shape) != shape):
+                raise ValueError("start/mach must both be contiguous int32 [pop][n_jobs][g] "
+                                 "tensors on the instance's device")
+    elif want_schedule:
         start = torch.full((pop, s.n_jobs, s.n_stages), -1, dtype=torch.int32, device=dev)
         mach = torch.full((pop, s.n_jobs, s.n_stages), -1, dtype=torch.int32, device=dev)
     if want_work:
@@ -231,12 +240,16 @@ def _decode_outputs(dinst, prio, want_schedule, want_work):
 
 def ffs_decode(dinst: DeviceInstance, prio: torch.Tensor, lds_slots: int = 0,
                want_schedule: bool = False, want_work: bool = False, workspace=None,
-               xy: bool = False):
+               xy: bool = False, start_out: torch.Tensor = None, mach_out: torch.Tensor = None):
     """Decode prio [pop, n_active] (int32, cuda), or with xy=True X/Y chromosomes
-    [pop, 2 * n_ops] (ffs_decode_xy). Returns obj (int64 [pop]) or a dict."""
+    [pop, 2 * n_ops] (ffs_decode_xy). Returns obj (int64 [pop]) or a dict.
+    start_out/mach_out: caller-owned [pop][n_jobs][g] plan arrays that receive the
+    decoded ops' start times and machines in place (frozen entries untouched)."""
     s = dinst.s
     dev = dinst.t["proc"].device
-    prio, pop, obj, start, mach, work = _decode_outputs(dinst, prio, want_schedule, want_work)
+    want_schedule = want_schedule or start_out is not None
+    prio, pop, obj, start, mach, work = _decode_outputs(dinst, prio, want_schedule, want_work,
+                                                        start_out, mach_out)
     need = _lib.ffs_decode_workspace_size(ctypes.byref(s), pop, int(lds_slots))
     if need == 0:
         raise FfsError(FFS_E_INVAL, "ffs_decode_workspace_size")

@@ -209,15 +209,19 @@ class Server:
         """Reschedule the shop for its next event and load it into r's slot."""
         ffsga = self.ffsga
         sh = self.shops[r.shop]
+        nxt = sh.inst
         if sh.event > 0:
             if not sh.arrivals:
                 raise ffsga.FfsError(ffsga.FFS_E_INVAL, f"shop {r.shop} has no arrival left")
             n = int(sh.inst.s.n_jobs)
             nxt = ffsga.reschedule(sh.inst, sh.plan_start[:n], sh.plan_mach[:n], sh.arrivals[0])
+        self.batch.set(r.slot, nxt, self.seed, r.shop, sh.event)
+        # the shop moves to its next event only once its slot holds it: a failed
+        # rescheduling or load leaves the shop, its plan and its arrivals as they were
+        if nxt is not sh.inst:
             sh.arrivals.pop(0)
             sh.inst = nxt
         r.event = sh.event
-        self.batch.set(r.slot, sh.inst, self.seed, r.shop, r.event)
         self.running[r.slot] = r
 
     def _finish(self, r: Request):
@@ -226,10 +230,9 @@ class Server:
         sh = self.shops[r.shop]
         prio, obj = self.batch.best(r.slot)
         n = int(sh.inst.s.n_jobs)
-        sched = ffsga.ffs_decode(sh.inst, prio.view(1, -1), want_schedule=True)
-        dec = sched["start"][0] >= 0
-        sh.plan_start[:n][dec] = sched["start"][0][dec]
-        sh.plan_mach[:n][dec] = sched["mach"][0][dec]
+        # decoded ops land in the executed plan; frozen entries keep their values
+        ffsga.ffs_decode(sh.inst, prio.view(1, -1), start_out=sh.plan_start[:n],
+                         mach_out=sh.plan_mach[:n])
         r.best_obj = int(obj.item())
         sh.history.append(r.best_obj)
         sh.event += 1
@@ -264,10 +267,14 @@ class Server:
         batched path, so that the requests that follow are arrival events; the
         metrics of this phase are returned and then cleared."""
         m = self.run([(0.0, s.sid) for s in self.shops if s.event == 0], log=log)
+        self.reset_metrics()
+        return m
+
+    def reset_metrics(self):
+        """Forget finished requests and counts (shops, plans and slots stay)."""
         self.requests = []
         self.decodes = 0
         self.ticks = 0
-        return m
 
     def run(self, schedule: Sequence[Tuple[float, int]], time_limit_s: Optional[float] = None,
             idle_sleep_s: float = 1e-4, log: Optional[Callable[[str], None]] = None,

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle_helpers import rescheduled_instance
 from paper_1903_10741_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -24,24 +25,7 @@ def _say(*a):
 
 
 def _event_instance(wl, k_events=1, seed=3):
-    """Instance after k_events arrivals, frozen on an oracle-decoded random plan."""
-    inst = wl.initial
-    g = inst.n_stages
-    plan_s = np.full((inst.n_jobs, g), -1, np.int32)
-    plan_m = np.full((inst.n_jobs, g), -1, np.int32)
-    for e in range(k_events):
-        prio = W.random_population(seed + e, 1, inst.n_active)[0]
-        _, s, m, _ = oracle.decode(inst, prio, want_schedule=True)
-        for j in inst.active:
-            f = inst.first_stage[j]
-            plan_s[j, f:] = s[j, f:]
-            plan_m[j, f:] = m[j, f:]
-        a = wl.arrivals[e]
-        inst = W.Instance.from_fields(oracle.reschedule(inst, plan_s, plan_m, a.rs, a.proc, a.power,
-                                                        a.release, a.due))
-        plan_s = np.vstack([plan_s, np.full((len(a.release), g), -1, np.int32)])
-        plan_m = np.vstack([plan_m, np.full((len(a.release), g), -1, np.int32)])
-    return inst
+    return rescheduled_instance(wl, k_events, seed)
 
 
 def _compare(inst, pop, lds_slots=0, schedule=True):
@@ -94,6 +78,21 @@ def test_decode_long_windows_span_several_chunks():
     inst = W.random_instance(5, n_jobs=20, n_stages=4, machines=[3, 5, 2, 4], p_max=200,
                              q_range=(3, 12), percent=45)
     _compare(inst, W.random_population(5, 32, 20))
+
+
+def test_decode_work_long_horizon_many_delays():
+    """Schedules of about 1.8 million slots (off chip) in which every op draws the
+    whole peak, so each is pushed right past the ops placed before it on the
+    other 15 machines of its stage: objectives, plans and work counts (about
+    4e7 examined slots per decode) equal the oracle's."""
+    _say("decode long horizon, every op pushed right")
+    rng = np.random.default_rng(17)
+    n, g, om = 300, 2, 16
+    proc = rng.integers(2000, 4001, size=(n, g, om)).astype(np.int32)
+    power = np.full((n, g, om), 7, np.int32)
+    inst = W.initial_instance(proc, power, np.zeros(n, np.int32), np.full(n, 10**6, np.int32),
+                              [om] * g, 7, 3)
+    _compare(inst, W.random_population(19, 8, n))
 
 
 def test_decode_sixteen_machines():

@@ -166,3 +166,24 @@ def test_ga_is_deterministic():
         ga.step(25)
         runs.append(_state(ga))
     _same(runs[0], runs[1], "determinism")
+
+
+def test_ga_auto_sized_profile_changes_nothing():
+    """FFS_LDS_AUTO (on-chip slots sized from generation 0's longest schedule)
+    gives the same populations as the default slots and the oracle; the chosen
+    slots hold 5/4 of that schedule and stay below the horizon."""
+    torch, ffsga = _ffs()
+    for cfg, gens in ((1, 12), (2, 20)):
+        wl = W.CONFIGS[cfg](2)
+        _say("GA with FFS_LDS_AUTO, config", cfg)
+        d = ffsga.DeviceInstance.from_host(wl.initial)
+        ga = ffsga.GA(d, ffsga.GaConfig.of(wl.ga, lds_slots=ffsga.FFS_LDS_AUTO), wl.seed, wl.shop, 0)
+        cap = int(ga.ga.lds_slots)
+        assert cap % 64 == 0 and 64 <= cap <= (d.horizon + 63) // 64 * 64
+        ga.step(gens)
+        ga.status()
+        ref = ffsga.GA(d, ffsga.GaConfig.of(wl.ga), wl.seed, wl.shop, 0)
+        ref.step(gens)
+        _same(_state(ga), _state(ref), f"auto vs default cfg {cfg}")
+        st = oracle.ga_run(wl.initial, wl.ga, wl.seed, wl.shop, 0, gens, n_threads=8)
+        _same(_state(ga), st, f"auto vs oracle cfg {cfg}")

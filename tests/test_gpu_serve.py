@@ -87,3 +87,28 @@ def test_serving_memory_budget_and_rejects_extra_events():
     assert m["done"] == 3 and m["failed"] == 1
     bad = [r for r in small.requests if r.status == "failed"][0]
     assert bad.shop == 0 and "arrival" in bad.error
+
+
+def test_failed_load_leaves_the_shop_unchanged():
+    """A shop whose rescheduled instance outgrows the batch's room: the request
+    fails, and the shop keeps its instance, executed plan, pending arrival and
+    event count, as if the request had never been admitted."""
+    from paper_1903_10741_amd.serve import Server
+    _say("serving: failed load rolls the shop back")
+    insts, arrs = _shops(61, 1, [1])
+    want = oracle.run_events(insts[0], arrs[0], GA, 2, 1, 0, n_threads=4, events=2)
+    room = oracle.horizon_bound(insts[0])
+    assert oracle.horizon_bound(want[1]["instance"]) > room   # event 1 does not fit
+    srv = Server(insts, arrs, GA, generations=2, n_slots=1, seed=1, max_horizon=room)
+    m = srv.run([(0.0, 0)])
+    assert m["done"] == 1 and m["failed"] == 0
+    sh = srv.shops[0]
+    inst0, plan_s, plan_m = sh.inst, sh.plan_start.clone(), sh.plan_mach.clone()
+    m = srv.run([(0.0, 0)])
+    assert m["failed"] == 1
+    bad = [r for r in srv.requests if r.status == "failed"][0]
+    assert "outside the limits" in bad.error
+    assert sh.inst is inst0 and sh.event == 1 and len(sh.arrivals) == 1
+    assert sh.history == [want[0]["best_obj"]]
+    assert (sh.plan_start == plan_s).all() and (sh.plan_mach == plan_m).all()
+    assert srv.adm.busy == 0 and not srv.running
