@@ -351,6 +351,78 @@ def bench_serve(args):
     return out
 
 
+def bench_rs_ratio(args):
+    """Section 5.3, Table 10: complete rescheduling (the method) against the
+    traditional static approach as the rescheduling point moves through the
+    original schedule. For each ratio r and each Table 5-shaped instance (10 jobs,
+    3 stages of 2 machines, power peak 4, WT = 100): the GA (64 islands of 8x8 =
+    4096, 100 generations) plans event 0, RS = round(r x that plan's makespan)
+    and round(r x 10) jobs arrive at RS; event 1 is then planned both ways by
+    the same GA (same seed) and the best objectives compared. Improvement ratio
+    = mean static objective / mean complete-rescheduling objective."""
+    import numpy as np
+    import torch
+    from paper_1903_10741_amd import ffsga
+    from paper_1903_10741_amd import workloads as W
+    gens = args.generations or 100
+    ga = W.TABLE5_GA
+    cfg = ffsga.GaConfig.of(ga)
+    paper = {0.2: (2727.61, 1195.29, 2.28), 0.4: (5608.31, 3745.06, 1.50),
+             0.6: (5464.86, 4673.57, 1.17), 0.8: (4805.43, 4755.91, 1.01)}
+    rows = []
+    t0 = time.perf_counter()
+    decodes = 0
+    for r in (0.2, 0.4, 0.6, 0.8):
+        st_obj, dy_obj = [], []
+        for sd in range(args.seed, args.seed + args.instances):
+            inst = W.table5_instance(sd)
+            d0 = ffsga.DeviceInstance.from_host(inst)
+            g0 = ffsga.GA(d0, cfg, sd, 0, 0)
+            g0.step(gens)
+            prio, _ = g0.best()
+            plan = ffsga.ffs_decode(d0, prio.view(1, -1), want_schedule=True)
+            ps, pm = plan["start"][0], plan["mach"][0]
+            p_np = np.asarray(inst.proc)
+            s_np, m_np = ps.cpu().numpy(), pm.cpu().numpy()
+            span = max(int(s_np[j, s]) + int(p_np[j, s, m_np[j, s]])
+                       for j in range(inst.n_jobs) for s in range(inst.n_stages))
+            rs = max(1, int(round(r * span)))
+            arr = W.table5_arrival(1000 + sd, inst, rs, max(1, int(round(r * inst.n_jobs))))
+            out = []
+            for static in (True, False):
+                d1 = ffsga.reschedule(d0, ps, pm, arr, static=static)
+                g1 = ffsga.GA(d1, cfg, sd, 0, 1)
+                g1.step(gens)
+                out.append(int(g1.best()[1].item()))
+            st_obj.append(out[0])
+            dy_obj.append(out[1])
+            decodes += 3 * (1 + gens) * ga.pop + 1
+        ms, md = float(np.mean(st_obj)), float(np.mean(dy_obj))
+        row = {"ratio": r, "instances": len(st_obj), "static_mean_obj": ms,
+               "rescheduling_mean_obj": md, "improvement_ratio": ms / md,
+               "instances_static_worse": int(sum(a > b for a, b in zip(st_obj, dy_obj))),
+               "instances_equal": int(sum(a == b for a, b in zip(st_obj, dy_obj))),
+               "paper": {"static": paper[r][0], "rescheduling": paper[r][1],
+                         "improvement_ratio": paper[r][2], "hardware": "Tesla K40 (their own "
+                         "random Table 5 instances, not these)"}}
+        progress(f"ratio {r}: static {ms:.1f}, rescheduling {md:.1f}, improvement {ms / md:.2f}")
+        rows.append(row)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = common(args, "improvement ratio of complete rescheduling over the static approach",
+                 float(np.mean([x["improvement_ratio"] for x in rows])),
+                 "x (mean static objective / mean rescheduling objective, averaged over ratios)",
+                 elapsed * 1e3, "int32", {
+                     "workload": f"Table 5-shaped instances {args.seed}-"
+                                 f"{args.seed + args.instances - 1} (10 jobs, 3 stages x 2 machines, "
+                                 f"Q_max 4, WT 100); GA 64 islands x 8x8, {gens} generations per "
+                                 f"event; arrivals of round(r x 10) jobs at RS = r x makespan",
+                     "decodes": decodes, "table": rows})
+    out["steps"] = 1
+    out["warmup"] = 0
+    return out
+
+
 def spearman(a, b):
     import numpy as np
     ra = np.argsort(np.argsort(a))
@@ -375,155 +447,199 @@ def populations(d, ga_cfg, seed, snap_gens):
     return torch.cat(prios), torch.cat(objs)
 
 
-def bench_surrogate(args):
-    """Time to reach the plain GA's final fitness, screened GA (4 candidates per cell,
-    the lowest surrogate score kept) against the plain GA, on paper-shaped event-0
-    instances of seeds 0..race_seeds-1, same GA seed, 500 generations each; per
-    instance the speedup is the plain GA's time to reach its own final objective
-    over the screened GA's time to reach it, and the value is the median.
-
-    Per instance (the value): --train-seeds networks are trained on 2.03 M
-    decoder-labelled chromosomes of that instance (the populations of 16 seeded
-    plain-GA runs at generations 0-30, or 0, 10, ..., 300 with --train-snapshots
-    spread), 2 epochs of Adam, network k from initial weights of seed k and its own
-    batch-order generator (seeded by instance and k, so no run depends on another);
-    each races the plain GA and the value is the median speedup over every
-    (instance, network) pair. Data and training time are reported apart. Across
-    instances (reported beside it): one network trained on instances of seeds
-    100-199 (generations 0, 10, 20, 40, 80 of one run each, 2.05 M chromosomes) and
-    raced on the same unseen instances."""
+def sg_train(model, data, gen, batch=4096, epochs=2, lr=1e-3):
+    """Adam on decoder-labelled chromosomes: `epochs` passes worth of batches, each
+    batch drawn from one instance's pairs (instance and rows from `gen`)."""
     import numpy as np
+    import torch
+    n_pairs = sum(int(x[1].shape[0]) for x in data)
+    steps = epochs * n_pairs // batch
+    losses = []
+    for _ in range(steps):
+        i = int(torch.randint(len(data), (1,), generator=gen))
+        feats, prio, tgt = data[i]
+        idx = torch.randint(prio.shape[0], (batch,), generator=gen).cuda()
+        losses.append(model.train_step(feats, prio[idx], tgt[idx], lr)[0])
+    torch.cuda.synchronize()
+    losses = [float(x.item()) for x in losses]
+    return steps, losses[0], float(np.mean(losses[-50:]))
+
+
+def sg_race(model, d, cfg, table, seed, screened, gens):
+    """One GA run from `seed`, best elite read every 10 generations:
+    [(generations, seconds, best objective)]."""
+    import torch
+    from paper_1903_10741_amd import ffsga
+    g = ffsga.GA(d, cfg, seed, 0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trace, done = [], 0
+    while done < gens:
+        k = min(10, gens - done)
+        if screened:
+            g.step_screened(model, table, 4, k)
+        else:
+            g.step(k)
+        done += k
+        trace.append((done, time.perf_counter() - t0, int(g.view()["elite_obj"].min().item())))
+    g.status()
+    return trace
+
+
+def sg_first(trace, target, offset=0.0):
+    """(generations, seconds + offset) at which a trace first reaches target."""
+    return next(((gn, t + offset) for gn, t, b in trace if b <= target), (None, None))
+
+
+def sg_evaluate(model, d, cfg, sd, plain, gens, tag, offset_s=0.0):
+    """Race the screened GA against a plain trace on one instance; held-out rank
+    correlation of the network's scores on two populations of another run.
+    offset_s: time charged to the screened run before it starts (data and training
+    of a network made for this very instance)."""
+    import numpy as np
+    pop = cfg.islands * cfg.rows * cfg.cols
+    table = model.score_table(model.features(d), d.n_active)
+    hp, ho = populations(d, cfg, 7777 + sd, (0, 20))
+    ys = model.score(table, hp).cpu().numpy()
+    ho = ho.cpu().numpy()
+    rho = [spearman(ys[k * pop:(k + 1) * pop], ho[k * pop:(k + 1) * pop]) for k in (0, 1)]
+    scr = sg_race(model, d, cfg, table, sd, True, gens)
+    target = plain[-1][2]
+    gp, tp = sg_first(plain, target)
+    gs, ts = sg_first(scr, target, offset_s)
+    progress(f"{tag} instance {sd}: plain {target} at gen {gp}, screened {scr[-1][2]}, "
+             f"reached at gen {gs}, rank correlation {rho[0]:.2f}/{rho[1]:.2f}")
+    return {"instance_seed": sd, "plain_final": target, "screened_final": scr[-1][2],
+            "plain_gens_to_target": gp, "plain_s_to_target": tp,
+            "screened_gens_to_target": gs, "screened_s_to_target": ts,
+            "speedup": (tp / ts) if ts else None, "heldout_spearman_gen0_20": rho,
+            "plain_s_per_gen": plain[-1][1] / plain[-1][0],
+            "screened_s_per_gen": scr[-1][1] / scr[-1][0]}
+
+
+def sg_summary(rows):
+    import numpy as np
+    sp = [r["speedup"] if r["speedup"] is not None else 0.0 for r in rows]
+    rho = np.array([r["heldout_spearman_gen0_20"] for r in rows])
+    return {"median_speedup": float(np.median(sp)), "runs": len(rows),
+            "reached": sum(r["screened_s_to_target"] is not None for r in rows),
+            "screened_better_final": sum(r["screened_final"] < r["plain_final"] for r in rows),
+            "heldout_spearman_median_gen0": float(np.median(rho[:, 0])),
+            "heldout_spearman_median_gen20": float(np.median(rho[:, 1])),
+            "per_instance": rows}
+
+
+def surrogate_cross(args, n_train, race_seeds, gens):
+    """Time to equal fitness by the cross-instance protocol: one network trained on
+    the populations (generations 0, 10, 20, 40, 80 of one plain run each) of
+    paper-shaped event-0 instances of seeds 100..100+n_train-1, then raced on the
+    unseen instances of seeds args.seed..: plain GA and screened GA (4 candidates
+    per cell) from the same GA seed; speedup = plain's time to its own final
+    objective / screened's time to reach it (0 if never). Data and training are
+    made once for every instance to come, so they are reported apart (amortised)."""
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
-    base = W.config2(0)
-    gens = args.generations or base.generations
-    cfg = ffsga.GaConfig.of(base.ga)
-    pop = base.ga.pop
-    B = 4096
-
-    def train(model, data, gen):
-        n_pairs = sum(int(x[1].shape[0]) for x in data)
-        steps = 2 * n_pairs // B
-        losses = []
-        for _ in range(steps):
-            i = int(torch.randint(len(data), (1,), generator=gen))
-            feats, prio, tgt = data[i]
-            idx = torch.randint(prio.shape[0], (B,), generator=gen).cuda()
-            losses.append(model.train_step(feats, prio[idx], tgt[idx], 1e-3)[0])
-        torch.cuda.synchronize()
-        losses = [float(x.item()) for x in losses]
-        return steps, losses[0], float(np.mean(losses[-50:]))
-
-    def race(model, d, table, seed, screened):
-        g = ffsga.GA(d, cfg, seed, 0, 0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        trace = []
-        done = 0
-        while done < gens:
-            k = min(10, gens - done)
-            if screened:
-                g.step_screened(model, table, 4, k)
-            else:
-                g.step(k)
-            done += k
-            best = int(g.view()["elite_obj"].min().item())
-            trace.append((done, time.perf_counter() - t0, best))
-        g.status()
-        return trace
-
-    def first(trace, target):
-        return next(((gn, t) for gn, t, b in trace if b <= target), (None, None))
-
-    def evaluate(model, d, sd, plain, tag):
-        table = model.score_table(model.features(d), d.n_active)
-        hp, ho = populations(d, cfg, 7777 + sd, (0, 20))
-        ys = model.score(table, hp).cpu().numpy()
-        ho = ho.cpu().numpy()
-        rho = [spearman(ys[k * pop:(k + 1) * pop], ho[k * pop:(k + 1) * pop]) for k in (0, 1)]
-        scr = race(model, d, table, sd, True)
-        target = plain[-1][2]
-        gp, tp = first(plain, target)
-        gs, ts = first(scr, target)
-        progress(f"{tag} instance {sd}: plain {target} at gen {gp}, screened {scr[-1][2]}, "
-                 f"reached at gen {gs}, rank correlation {rho[0]:.2f}/{rho[1]:.2f}")
-        return {"instance_seed": sd, "plain_final": target, "screened_final": scr[-1][2],
-                "plain_gens_to_target": gp, "plain_s_to_target": tp,
-                "screened_gens_to_target": gs, "screened_s_to_target": ts,
-                "speedup": (tp / ts) if ts else None, "heldout_spearman_gen0_20": rho,
-                "plain_s_per_gen": plain[-1][1] / plain[-1][0],
-                "screened_s_per_gen": scr[-1][1] / scr[-1][0]}
-
-    def summary(rows):
-        sp = [r["speedup"] if r["speedup"] is not None else 0.0 for r in rows]
-        return {"median_speedup": float(np.median(sp)), "runs": len(rows),
-                "reached": sum(r["screened_s_to_target"] is not None for r in rows),
-                "screened_better_final": sum(r["screened_final"] < r["plain_final"] for r in rows),
-                "per_instance": rows}
-
-    # the cross-instance network: trained once on instances 100..
+    cfg = ffsga.GaConfig.of(W.config2(0).ga)
+    pop = cfg.islands * cfg.rows * cfg.cols
+    model = ffsga.Surrogate(W.surrogate_init(args.seed))
+    gen = torch.Generator(device="cpu").manual_seed(args.seed)
     t0 = time.perf_counter()
-    cross = ffsga.Surrogate(W.surrogate_init(args.seed))
-    cross_gen = torch.Generator(device="cpu").manual_seed(args.seed)
     data = []
-    for sd in range(100, 100 + args.train_instances):
+    for sd in range(100, 100 + n_train):
         d = ffsga.DeviceInstance.from_host(W.config2(sd).initial)
         prio, obj = populations(d, cfg, sd, (0, 10, 20, 40, 80))
-        data.append((cross.features(d), prio, cross.targets(obj, pop)))
-    cross_pairs = sum(int(x[1].shape[0]) for x in data)
-    cross_fit = train(cross, data, cross_gen)
+        data.append((model.features(d), prio, model.targets(obj, pop)))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    pairs = sum(int(x[1].shape[0]) for x in data)
+    t1 = time.perf_counter()
+    fit = sg_train(model, data, gen)
+    t_train = time.perf_counter() - t1
     del data
-    t_cross = time.perf_counter() - t0
-    progress(f"cross-instance network: {cross_pairs} pairs, {cross_fit[0]} steps, "
-             f"loss {cross_fit[1]:.3f} -> {cross_fit[2]:.3f}, {t_cross:.1f} s")
-    own_rows, cross_rows, prep = [], [], []
-    for sd in range(args.seed, args.seed + args.race_seeds):
+    progress(f"cross-instance network: {pairs} pairs, {fit[0]} steps, loss {fit[1]:.3f} -> "
+             f"{fit[2]:.3f}, data {t_data:.1f} s, training {t_train:.1f} s")
+    rows = []
+    for k, sd in enumerate(range(args.seed, args.seed + race_seeds)):
         d = ffsga.DeviceInstance.from_host(W.config2(sd).initial)
-        t0 = time.perf_counter()
-        feats = cross.features(d)
-        data = []
-        snaps = tuple(range(31)) if args.train_snapshots == "early" else tuple(range(0, 301, 10))
-        for rs in range(1000, 1016):
-            prio, obj = populations(d, cfg, rs, snaps)
-            data.append((feats, prio, cross.targets(obj, pop)))
-        torch.cuda.synchronize()
-        t_data = time.perf_counter() - t0
-        plain = None
+        if k == 0:   # warm-up of both paths
+            table = model.score_table(model.features(d), d.n_active)
+            sg_race(model, d, cfg, None, sd, False, 20)
+            sg_race(model, d, cfg, table, sd, True, 20)
+        plain = sg_race(model, d, cfg, None, sd, False, gens)
+        rows.append(sg_evaluate(model, d, cfg, sd, plain, gens, "cross-instance network"))
+    out = sg_summary(rows)
+    out.update({"protocol": f"one network trained on instances {100}-{99 + n_train} "
+                            f"(generations 0, 10, 20, 40, 80 of one plain run each), raced on "
+                            f"unseen instances {args.seed}-{args.seed + race_seeds - 1}; data and "
+                            f"training amortised over every instance to come, reported apart",
+                "train_pairs": pairs, "train_steps": fit[0], "loss_first": fit[1],
+                "loss_last50": fit[2], "data_s": t_data, "train_s": t_train})
+    return out
+
+
+def bench_surrogate(args):
+    """Time to reach the plain GA's final fitness, screened GA (4 candidates per cell,
+    the lowest surrogate score kept) against the plain GA, on paper-shaped event-0
+    instances of seeds 0..race_seeds-1, same GA seed, 500 generations each.
+
+    The value is the median speedup of one network trained across instances
+    (seeds 100-199) and raced on the unseen ones (surrogate_cross). Beside it,
+    per instance, --train-seeds networks trained on that instance itself (the
+    populations of 16 seeded plain-GA runs at generations 0-30, or 0, 10, ...,
+    300 with --train-snapshots spread; 2.03 M pairs, 2 epochs of Adam; network k
+    from initial weights of seed k and its own batch-order generator): such a
+    network serves one instance only, so its data generation and training count
+    in its time to the target."""
+    import torch
+    from paper_1903_10741_amd import ffsga
+    from paper_1903_10741_amd import workloads as W
+    gens = args.generations or W.config2(0).generations
+    cross = surrogate_cross(args, args.train_instances, args.race_seeds, gens)
+    cfg = ffsga.GaConfig.of(W.config2(0).ga)
+    pop = cfg.islands * cfg.rows * cfg.cols
+    own_rows, prep = [], []
+    for sd in range(args.seed, args.seed + (args.race_seeds if args.train_seeds > 0 else 0)):
+        d = ffsga.DeviceInstance.from_host(W.config2(sd).initial)
+        plain = sg_race(None, d, cfg, None, sd, False, gens)
         for k in range(args.train_seeds):
-            t1 = time.perf_counter()
+            t0 = time.perf_counter()
             model = ffsga.Surrogate(W.surrogate_init(k))
-            fit = train(model, data, torch.Generator(device="cpu").manual_seed(1_000_003 * sd + k))
+            feats = model.features(d)
+            data = []
+            snaps = tuple(range(31)) if args.train_snapshots == "early" else tuple(range(0, 301, 10))
+            for rs in range(1000, 1016):
+                prio, obj = populations(d, cfg, rs, snaps)
+                data.append((feats, prio, model.targets(obj, pop)))
+            torch.cuda.synchronize()
+            t_data = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            fit = sg_train(model, data, torch.Generator(device="cpu").manual_seed(1_000_003 * sd + k))
+            t_train = time.perf_counter() - t1
+            del data
             prep.append({"instance_seed": sd, "train_seed": k, "data_s": t_data,
-                         "train_s": time.perf_counter() - t1, "steps": fit[0], "loss_first": fit[1],
+                         "train_s": t_train, "steps": fit[0], "loss_first": fit[1],
                          "loss_last50": fit[2]})
-            if plain is None:
-                if sd == args.seed:   # warm-up of both paths
-                    race(model, d, None, sd, False)
-                    race(model, d, model.score_table(feats, d.n_active), sd, True)
-                plain = race(model, d, None, sd, False)
-            row = evaluate(model, d, sd, plain, f"own-instance network {k}")
+            row = sg_evaluate(model, d, cfg, sd, plain, gens, f"own-instance network {k}",
+                              offset_s=t_data + t_train)
             row["train_seed"] = k
             own_rows.append(row)
-        del data
-        cross_rows.append(evaluate(cross, d, sd, plain, "cross-instance network"))
-    own, crs = summary(own_rows), summary(cross_rows)
-    out = common(args, "time-to-equal-fitness, surrogate vs plain GA", own["median_speedup"],
+    out = common(args, "time-to-equal-fitness, surrogate vs plain GA", cross["median_speedup"],
                  "x (plain GA time / screened GA time to the plain GA's final objective)",
-                 (sum(r["screened_s_per_gen"] for r in own_rows)
-                  + sum(r["plain_s_per_gen"] for r in own_rows if r["train_seed"] == 0)) * gens * 1e3,
+                 sum(r["screened_s_per_gen"] for r in cross["per_instance"]) * gens * 1e3
+                 / max(len(cross["per_instance"]), 1),
                  "bf16/fp32 surrogate, int32 decode", {
                      "workload": "paper-shaped event 0 (50 jobs, 5 stages, 3 machines), 32 islands "
                                  f"x 8x16, {gens} generations, screened: 4 candidates per cell; "
-                                 f"instances {args.seed}-{args.seed + args.race_seeds - 1}, "
-                                 f"{args.train_seeds} own-instance networks each; value: median over "
-                                 "(instance, network) pairs of the speedup (0 where the screened "
-                                 "run never reaches the target)",
-                     "own_instance": {**own, "training": prep,
-                                      "train_snapshots": args.train_snapshots},
-                     "cross_instance": {**crs, "train_pairs": cross_pairs, "train_steps": cross_fit[0],
-                                        "loss_first": cross_fit[1], "loss_last50": cross_fit[2],
-                                        "data_and_train_s": t_cross}})
+                                 f"raced on instances {args.seed}-{args.seed + args.race_seeds - 1}; "
+                                 "value: median over them of the speedup of the cross-instance "
+                                 "network (0 where the screened run never reaches the target)",
+                     "cross_instance": cross})
+    if own_rows:
+        out["config"]["own_instance"] = {**sg_summary(own_rows), "training": prep,
+                                         "train_snapshots": args.train_snapshots,
+                                         "note": "data generation and training of each network "
+                                                 "are inside its time to the target"}
     out["steps"] = 1
     out["warmup"] = 1
     return out
@@ -535,7 +651,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "paper", "batch", "serve", "surrogate"],
+                    choices=["large", "paper", "batch", "serve", "surrogate", "rs-ratio"],
                     help="large (default): the large-200x10x4-6 event loop, one event per step, "
                          "with the paper-shaped workload measured beside it")
     ap.add_argument("--lds-slots", type=int, default=0)
@@ -549,6 +665,8 @@ def main():
     ap.add_argument("--no-paper", action="store_true",
                     help="large workload: skip the paper-shaped measurement beside it")
     ap.add_argument("--paper-steps", type=int, default=2)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="large workload: skip the surrogate's time-to-equal-fitness beside it")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--generations", type=int, default=None,
                     help="override generations per event (profiling runs only)")
@@ -559,6 +677,8 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--race-seeds", type=int, default=10)
+    ap.add_argument("--instances", type=int, default=20,
+                    help="rs-ratio: Table 5-shaped instances per ratio")
     ap.add_argument("--train-instances", type=int, default=100)
     ap.add_argument("--train-seeds", type=int, default=3,
                     help="surrogate: own-instance networks per instance (initial weights and "
@@ -590,6 +710,9 @@ def main():
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args)), flush=True)
         return
+    if args.workload == "rs-ratio":
+        print(json.dumps(bench_rs_ratio(args)), flush=True)
+        return
     if args.workload == "paper":
         out = bench_paper(args, args.steps, args.warmup)
         if not args.no_cpu_baseline:
@@ -607,6 +730,20 @@ def main():
         out["paper_shaped"] = {k: paper[k] for k in ("value", "unit", "steps", "warmup",
                                                      "ms_per_step", "config", "roofline",
                                                      "cpu_baseline") if k in paper}
+    if not args.no_surrogate:
+        progress("surrogate: time to equal fitness (cross-instance network)")
+        sg = surrogate_cross(args, args.train_instances, args.race_seeds, 500)
+        out["surrogate_time_to_equal_fitness"] = {
+            "metric": "time-to-equal-fitness, surrogate vs plain GA",
+            "value": sg["median_speedup"],
+            "unit": "x (plain GA time / screened GA time to the plain GA's final objective; "
+                    "0 where never reached)",
+            **{k: v for k, v in sg.items() if k != "per_instance"},
+            "per_instance": [{k: r[k] for k in ("instance_seed", "speedup",
+                                                  "plain_gens_to_target",
+                                                  "screened_gens_to_target",
+                                                  "heldout_spearman_gen0_20")}
+                             for r in sg["per_instance"]]}
     if not args.no_cpu_baseline:
         from paper_1903_10741_amd import workloads as W
         progress("CPU oracle (large workload, event 0)")

@@ -72,6 +72,10 @@ typedef struct {
                                        g - first_stage; set by ffs_prepare and reschedule */
   int32_t decode_rules;             /* host: FFS_RULE_* bits, variants of the job-priority
                                        decode (0 = the default rules); reschedule copies it */
+  int32_t n_fixed;                  /* planned ops kept where the plan put them (written by
+                                       reschedule_static; 0 otherwise) */
+  const int32_t *fixed;             /* device [n_fixed][3]: (start, end, q) with
+                                       RS <= start < end: power q held on [start, end) */
 } ffs_instance;
 
 /* Variants of the job-priority decode, readings the paper leaves open (X/Y
@@ -272,6 +276,24 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
                int32_t rs, int32_t n_new, const int32_t *new_proc, const int32_t *new_power,
                const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
                void *workspace, size_t workspace_bytes, void *stream);
+
+/* The traditional static approach (Section 4.3, Fig. 7; Section 5.3), the
+ * comparison the paper draws against complete rescheduling: the executed plan
+ * of every job known before rs stays as it is, started or not, and the n_new
+ * arrivals are scheduled after it: a new job's op at stage s starts no
+ * earlier than the completion of the plan's last op at stage s. Every old
+ * job is frozen whole (its objective terms go to frozen_tardiness and
+ * frozen_cmax); its ops running at rs hold their power on [rs, end)
+ * (running), those starting at or after rs on their planned windows
+ * (fixed); every machine of stage s is free from the stage's planned
+ * completion; the active jobs are the arrivals. Arguments, synchronisation and
+ * errors as reschedule; next->fixed: caller-filled device pointer with room
+ * for prev->n_jobs * g triples (the library writes next->n_fixed). */
+int reschedule_static(const ffs_instance *prev, const int32_t *plan_start,
+                      const int32_t *plan_mach, int32_t rs, int32_t n_new,
+                      const int32_t *new_proc, const int32_t *new_power,
+                      const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
+                      void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched GA: many independent instances (shops) advanced by the same

@@ -48,6 +48,7 @@ class _Instance(ctypes.Structure):
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
         ("n_active", ctypes.c_int32), ("active", _i32p),
         ("decode_rules", ctypes.c_int32),
+        ("n_fixed", ctypes.c_int32), ("fixed", _i32p),
     ]
 
 
@@ -71,6 +72,7 @@ class _ReschedOut(ctypes.Structure):
         ("machine_free", _i32p), ("running", _i32p), ("active", _i32p),
         ("n_jobs", ctypes.c_int32), ("n_running", ctypes.c_int32), ("n_active", ctypes.c_int32),
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
+        ("fixed", _i32p), ("n_fixed", ctypes.c_int32),
     ]
 
 
@@ -125,8 +127,10 @@ def _load():
     lib.orc_reschedule.argtypes = [ctypes.POINTER(_Instance), _i32p, _i32p, ctypes.c_int32,
                                    ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
                                    ctypes.POINTER(_ReschedOut)]
+    lib.orc_reschedule_static.argtypes = lib.orc_reschedule.argtypes
     for f in ("orc_decode", "orc_decode_pop", "orc_decode_ops", "orc_ga_init",
               "orc_ga_generation", "orc_ga_breed", "orc_ga_finish", "orc_reschedule",
+              "orc_reschedule_static",
               "orc_xy_order", "orc_decode_xy", "orc_decode_xy_pop"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -160,6 +164,8 @@ class _Pinned:
             "running": _arr(inst.running).reshape(-1, 2) if len(inst.running) else np.zeros((1, 2), np.int32),
             "active": _arr(inst.active).reshape(-1) if len(inst.active) else np.zeros(1, np.int32),
         }
+        fixed = np.asarray(getattr(inst, "fixed", np.zeros((0, 3), np.int32))).reshape(-1, 3)
+        self.keep["fixed"] = _arr(fixed) if len(fixed) else np.zeros((1, 3), np.int32)
         k = self.keep
         self.s = _Instance(
             n, g, om, _ptr(k["n_machines"]), _ptr(k["proc"]), _ptr(k["power"]),
@@ -167,7 +173,7 @@ class _Pinned:
             _ptr(k["first_stage"]), _ptr(k["ready"]), _ptr(k["machine_free"]),
             int(len(inst.running)), _ptr(k["running"]), int(inst.frozen_tardiness),
             int(inst.frozen_cmax), int(len(inst.active)), _ptr(k["active"]),
-            int(getattr(inst, "decode_rules", 0)))
+            int(getattr(inst, "decode_rules", 0)), int(len(fixed)), _ptr(k["fixed"]))
         self.n_active = int(len(inst.active))
         self.n_jobs = n
         self.g = g
@@ -470,8 +476,11 @@ def mutate(v, w1, w2):
     return v
 
 
-def reschedule(prev, plan_start, plan_mach, rs, new_proc, new_power, new_release, new_due):
-    """Freeze the executed plan at rs and append new jobs. Returns a dict of instance fields."""
+def reschedule(prev, plan_start, plan_mach, rs, new_proc, new_power, new_release, new_due,
+               static=False):
+    """Freeze the executed plan at rs and append new jobs. Returns a dict of instance fields.
+    static=True: the traditional static approach (orc_reschedule_static): the whole plan
+    of the known jobs stays in place and the arrivals go after each stage's planned ops."""
     lib = _load()
     p = _Pinned(prev)
     g = p.g
@@ -492,13 +501,15 @@ def reschedule(prev, plan_start, plan_mach, rs, new_proc, new_power, new_release
         "first_stage": np.zeros(max(n, 1), np.int32), "ready": np.zeros(max(n, 1), np.int32),
         "machine_free": np.zeros((g, om), np.int32), "running": np.zeros((cap, 2), np.int32),
         "active": np.zeros(max(n, 1), np.int32),
+        "fixed": np.zeros((max(p.n_jobs * g, 1), 3), np.int32),
     }
     out = _ReschedOut(*[_ptr(bufs[k]) for k in ("proc", "power", "release", "due", "first_stage",
                                                  "ready", "machine_free", "running", "active")],
-                      0, 0, 0, 0, 0)
-    rc = lib.orc_reschedule(p.ref(), _ptr(ps), _ptr(pm), int(rs), n_new, _ptr(nproc), _ptr(npow),
-                            _ptr(nrel), _ptr(ndue), ctypes.byref(out))
-    _check(rc, "orc_reschedule")
+                      0, 0, 0, 0, 0, _ptr(bufs["fixed"]), 0)
+    fn = lib.orc_reschedule_static if static else lib.orc_reschedule
+    rc = fn(p.ref(), _ptr(ps), _ptr(pm), int(rs), n_new, _ptr(nproc), _ptr(npow),
+            _ptr(nrel), _ptr(ndue), ctypes.byref(out))
+    _check(rc, "orc_reschedule_static" if static else "orc_reschedule")
     return {
         "n_jobs": n, "n_stages": g, "o_max": om, "n_machines": _arr(prev.n_machines).copy(),
         "proc": bufs["proc"][:n].copy(), "power": bufs["power"][:n].copy(),
@@ -509,14 +520,18 @@ def reschedule(prev, plan_start, plan_mach, rs, new_proc, new_power, new_release
         "running": bufs["running"][:out.n_running].copy(),
         "frozen_tardiness": int(out.frozen_tardiness), "frozen_cmax": int(out.frozen_cmax),
         "active": bufs["active"][:out.n_active].copy(),
+        "fixed": bufs["fixed"][:out.n_fixed].copy(),
     }
 
 
-def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, events=None):
+def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, events=None,
+               static=False):
     """The predictive-reactive loop (Section 4.1) on the oracle: for each event,
     run the GA (generation 0 then `generations`), execute the best elite's
     plan until the next arrival, freeze and reschedule. Returns one dict per
-    event: best_obj, best_prio, the instance dict and the plan after the event."""
+    event: best_obj, best_prio, the instance dict and the plan after the event.
+    static=True: each arrival is handled by the traditional static approach
+    instead (reschedule(..., static=True))."""
     inst = initial
     g = int(initial.n_stages)
     plan_s = np.full((int(initial.n_jobs), g), -1, np.int32)
@@ -537,7 +552,8 @@ def run_events(initial, arrivals, ga, generations, seed, shop=0, n_threads=1, ev
                      "plan_start": plan_s.copy(), "plan_mach": plan_m.copy()})
         if e + 1 < n_events and e < len(arrivals):
             a = arrivals[e]
-            nxt = reschedule(inst, plan_s, plan_m, a.rs, a.proc, a.power, a.release, a.due)
+            nxt = reschedule(inst, plan_s, plan_m, a.rs, a.proc, a.power, a.release, a.due,
+                             static=static)
             k = len(a.release)
             plan_s = np.vstack([plan_s, np.full((k, g), -1, np.int32)])
             plan_m = np.vstack([plan_m, np.full((k, g), -1, np.int32)])

@@ -74,8 +74,14 @@ static uint32_t draw_below(uint64_t w, uint32_t n) {
 
 static int check_instance(const orc_instance *in) {
   if (in->n_stages < 1 || in->o_max < 1 || in->n_jobs < 0 || in->n_active < 0 ||
-      in->n_active > in->n_jobs || in->n_running < 0 || in->q_max < 1)
+      in->n_active > in->n_jobs || in->n_running < 0 || in->q_max < 1 || in->n_fixed < 0 ||
+      (in->n_fixed > 0 && !in->fixed))
     return ORC_E_INVAL;
+  for (int r = 0; r < in->n_fixed; ++r) {
+    const int32_t st = in->fixed[3 * r], end = in->fixed[3 * r + 1], q = in->fixed[3 * r + 2];
+    if (st < in->rs || end <= st || q < 1) return ORC_E_INVAL;
+    if (q > in->q_max) return ORC_E_INFEASIBLE;
+  }
   for (int s = 0; s < in->n_stages; ++s)
     if (in->n_machines[s] < 1 || in->n_machines[s] > in->o_max) return ORC_E_INVAL;
   for (int k = 0; k < in->n_active; ++k) {
@@ -111,6 +117,7 @@ int64_t orc_horizon_bound(const orc_instance *in) {
     for (int m = 0; m < in->n_machines[s]; ++m)
       base = MAX32(base, (int64_t)in->machine_free[s * in->o_max + m]);
   for (int r = 0; r < in->n_running; ++r) base = MAX32(base, (int64_t)in->running[2 * r]);
+  for (int r = 0; r < in->n_fixed; ++r) base = MAX32(base, (int64_t)in->fixed[3 * r + 1]);
   int64_t sum = 0;
   for (int k = 0; k < in->n_active; ++k) {
     int j = in->active[k];
@@ -166,6 +173,12 @@ static int decoder_init(decoder *d, const orc_instance *in) {
   for (int r = 0; r < in->n_running; ++r) {
     int32_t end = in->running[2 * r], q = in->running[2 * r + 1];
     for (int64_t tau = 0; tau < (int64_t)end - in->rs; ++tau) d->profile[tau] += q;
+  }
+  /* planned ops kept in place (static approach): power on their own window */
+  for (int r = 0; r < in->n_fixed; ++r) {
+    const int32_t st = in->fixed[3 * r], end = in->fixed[3 * r + 1], q = in->fixed[3 * r + 2];
+    for (int64_t tau = (int64_t)st - in->rs; tau < (int64_t)end - in->rs; ++tau)
+      d->profile[tau] += q;
   }
   return ORC_OK;
 }
@@ -934,6 +947,73 @@ int orc_reschedule(const orc_instance *prev, const int32_t *plan_start,
       out->frozen_cmax = MAX32(out->frozen_cmax, last_end);
     }
   }
+  for (int32_t i = 0; i < n_new; ++i) {
+    out->first_stage[n0 + i] = 0;
+    out->ready[n0 + i] = new_release[i];
+  }
+  out->n_active = 0;
+  for (int32_t j = 0; j < n; ++j)
+    if (out->first_stage[j] < g) out->active[out->n_active++] = j;
+  return ORC_OK;
+}
+
+int orc_reschedule_static(const orc_instance *prev, const int32_t *plan_start,
+                          const int32_t *plan_mach, int32_t rs, int32_t n_new,
+                          const int32_t *new_proc, const int32_t *new_power,
+                          const int32_t *new_release, const int32_t *new_due,
+                          orc_resched_out *out) {
+  const int32_t g = prev->n_stages, om = prev->o_max, n0 = prev->n_jobs;
+  if (n_new < 0 || rs < prev->rs || g < 1 || om < 1) return ORC_E_INVAL;
+  const int32_t n = n0 + n_new;
+  const size_t per_job = (size_t)g * om;
+  memcpy(out->proc, prev->proc, sizeof(int32_t) * per_job * n0);
+  memcpy(out->power, prev->power, sizeof(int32_t) * per_job * n0);
+  memcpy(out->proc + per_job * n0, new_proc, sizeof(int32_t) * per_job * n_new);
+  memcpy(out->power + per_job * n0, new_power, sizeof(int32_t) * per_job * n_new);
+  memcpy(out->release, prev->release, sizeof(int32_t) * n0);
+  memcpy(out->due, prev->due, sizeof(int32_t) * n0);
+  memcpy(out->release + n0, new_release, sizeof(int32_t) * n_new);
+  memcpy(out->due + n0, new_due, sizeof(int32_t) * n_new);
+  out->n_jobs = n;
+  out->n_running = 0;
+  out->n_fixed = 0;
+  out->frozen_tardiness = 0;
+  out->frozen_cmax = 0;
+  /* completion of the plan's last op at each stage */
+  int32_t *stage_end = (int32_t *)calloc((size_t)g, sizeof(int32_t));
+  if (!stage_end) return ORC_E_NOMEM;
+  for (int32_t j = 0; j < n0; ++j) {
+    int32_t last_end = prev->release[j];
+    for (int32_t s = 0; s < g; ++s) {
+      const int32_t m = plan_mach[(int64_t)j * g + s], st = plan_start[(int64_t)j * g + s];
+      if (m < 0 || m >= prev->n_machines[s] || st < 0) {
+        free(stage_end);
+        return ORC_E_INVAL;
+      }
+      const int32_t end = st + prev->proc[((int64_t)j * g + s) * om + m];
+      const int32_t q = prev->power[((int64_t)j * g + s) * om + m];
+      stage_end[s] = MAX32(stage_end[s], end);
+      if (st < rs && end > rs) {  /* running at RS: power on [RS, end) */
+        out->running[2 * out->n_running] = end;
+        out->running[2 * out->n_running + 1] = q;
+        out->n_running++;
+      } else if (st >= rs) {      /* not started: power on its planned window */
+        out->fixed[3 * out->n_fixed] = st;
+        out->fixed[3 * out->n_fixed + 1] = end;
+        out->fixed[3 * out->n_fixed + 2] = q;
+        out->n_fixed++;
+      }
+      last_end = end;
+    }
+    out->first_stage[j] = g;
+    out->ready[j] = last_end;
+    const int32_t late = last_end - prev->due[j];
+    out->frozen_tardiness += late > 0 ? late : 0;
+    out->frozen_cmax = MAX32(out->frozen_cmax, last_end);
+  }
+  for (int32_t s = 0; s < g; ++s)
+    for (int32_t m = 0; m < om; ++m) out->machine_free[s * om + m] = m < prev->n_machines[s] ? stage_end[s] : 0;
+  free(stage_end);
   for (int32_t i = 0; i < n_new; ++i) {
     out->first_stage[n0 + i] = 0;
     out->ready[n0 + i] = new_release[i];

@@ -48,6 +48,10 @@ typedef struct {
   int32_t n_active;
   const int32_t *active;       /* [n_active] job ids with first_stage < g; gene k <-> active[k] */
   int32_t decode_rules;        /* job-vector decode variants, ORC_RULE_* bits (0 = the default) */
+  int32_t n_fixed;
+  const int32_t *fixed;        /* [n_fixed][3] (start, end, q): planned ops that stay where the
+                                  plan put them (the traditional static approach), power q held on
+                                  [start, end) with RS <= start < end */
 } orc_instance;
 
 /* Variants of the job-vector decode (readings the paper leaves open):
@@ -183,6 +187,8 @@ typedef struct {
   int32_t n_jobs, n_running, n_active;
   int64_t frozen_tardiness;
   int32_t frozen_cmax;
+  int32_t *fixed;              /* [n_jobs * g][3], orc_reschedule_static only */
+  int32_t n_fixed;
 } orc_resched_out;
 
 int orc_reschedule(const orc_instance *prev, const int32_t *plan_start,
@@ -190,6 +196,22 @@ int orc_reschedule(const orc_instance *prev, const int32_t *plan_start,
                    const int32_t *new_proc, const int32_t *new_power,
                    const int32_t *new_release, const int32_t *new_due,
                    orc_resched_out *out);
+
+/* The traditional static approach (Section 4.3, Fig. 7; Section 5.3), the
+ * comparison the paper draws against complete rescheduling: the executed
+ * plan of every job known before rs stays as it is, started or not, and the
+ * n_new arrivals are scheduled after it, a new job's op at stage s no earlier
+ * than the completion of the plan's last op at stage s ("after completing the
+ * operations of the original schedule at each stage"). Every old job is
+ * frozen whole: its ops running at rs hold their power on [rs, end)
+ * (running), those starting at or after rs on their planned window (fixed);
+ * every machine of stage s is free from the stage's planned completion. The
+ * next instance's active jobs are the arrivals. */
+int orc_reschedule_static(const orc_instance *prev, const int32_t *plan_start,
+                          const int32_t *plan_mach, int32_t rs, int32_t n_new,
+                          const int32_t *new_proc, const int32_t *new_power,
+                          const int32_t *new_release, const int32_t *new_due,
+                          orc_resched_out *out);
 
 #ifdef __cplusplus
 }

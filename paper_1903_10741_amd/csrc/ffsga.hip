@@ -70,7 +70,7 @@ struct Header {
   int32_t frozen_cmax, n_running, n_active, n_ops;  // n_ops: unfrozen ops (ffs_prepare)
   unsigned long long work;  // algorithmic work of every decode of a GA
   int32_t span_max;     // longest schedule (end - RS) of a sizing decode (FFS_LDS_AUTO)
-  int32_t pad1;
+  int32_t n_fixed;      // planned ops kept in place (reschedule_static)
 };
 static_assert(sizeof(Header) <= kHeaderBytes, "header");
 
@@ -133,8 +133,9 @@ struct DInst {
   const int32_t *mfree;      // [g][om]
   const int32_t *running;    // [nr][2]
   const int32_t *active;     // [n]
+  const int32_t *fixed;      // [nf][3]: (start, end, q) of planned ops kept in place
   int64_t frozen_t;
-  int32_t n_jobs, g, om, omp, q_max, wt, rs, nr, n, frozen_cmax, horizon;
+  int32_t n_jobs, g, om, omp, q_max, wt, rs, nr, n, frozen_cmax, horizon, nf;
   int32_t rules;  // FFS_RULE_* decode variants (job-priority chromosomes)
 };
 
@@ -163,6 +164,9 @@ struct LdsProfile {
   __device__ void commit(int t, int p, int q) const;
   __device__ void add_running(int len, int q) const {
     for (int x = __lane_id(); x < len; x += kWave) add(x, (uint32_t)q);
+  }
+  __device__ void add_span(int a, int b, int q) const {
+    for (int x = a + __lane_id(); x < b; x += kWave) add(x, (uint32_t)q);
   }
 };
 
@@ -203,6 +207,9 @@ struct GlobalProfile {
   __device__ void commit(int t, int p, int q) const;
   __device__ void add_running(int len, int q) const {
     for (int x = __lane_id(); x < len; x += kWave) add(x, (uint32_t)q);
+  }
+  __device__ void add_span(int a, int b, int q) const {
+    for (int x = a + __lane_id(); x < b; x += kWave) add(x, (uint32_t)q);
   }
 };
 
@@ -376,7 +383,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   }
   if (ballot64(bad)) return kDecInval;
 
-  // Power held by the ops running at RS, on [RS, end).
+  // Power held by the ops running at RS, on [RS, end), and by the planned ops
+  // kept in place (the static approach), on their own windows.
   prof.clear();
   prof.order();
   for (int r = 0; r < I.nr; ++r) {
@@ -384,6 +392,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     const uint32_t q = (uint32_t)ld_const(I.running, 2 * r + 1);
     if (len > prof.cap) return kDecOverflow;
     prof.add_running(len, (int)q);
+  }
+  for (int r = 0; r < I.nf; ++r) {
+    const int b = ld_const(I.fixed, 3 * r + 1) - I.rs;
+    if (b > prof.cap) return kDecOverflow;
+    prof.add_span(ld_const(I.fixed, 3 * r) - I.rs, b, ld_const(I.fixed, 3 * r + 2));
   }
   prof.order();
 
@@ -1112,6 +1125,11 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     const int len = ld_const(I.running, 2 * r) - I.rs;
     if (len > prof.cap) return kDecOverflow;
     prof.add_running(len, ld_const(I.running, 2 * r + 1));
+  }
+  for (int r = 0; r < I.nf; ++r) {
+    const int b = ld_const(I.fixed, 3 * r + 1) - I.rs;
+    if (b > prof.cap) return kDecOverflow;
+    prof.add_span(ld_const(I.fixed, 3 * r) - I.rs, b, ld_const(I.fixed, 3 * r + 2));
   }
   prof.order();
   __asm__ volatile("" ::: "memory");
@@ -1939,6 +1957,8 @@ __global__ void pack_kernel(const int32_t *proc, const int32_t *power, uint32_t 
 struct PrepArgs {
   const int32_t *nm, *proc, *power, *first, *ready, *mfree, *running, *active;
   int32_t n_jobs, g, om, q_max, rs, nr, n;
+  const int32_t *fixed;
+  int32_t nf;
 };
 
 __device__ void block_reduce_i64(int64_t v, int64_t *sh, bool is_max, int64_t &out) {
@@ -1999,6 +2019,12 @@ __device__ void prepare_body(const PrepArgs &a, Header *h) {
   for (int x = threadIdx.x; x < a.g * a.om; x += blockDim.x)
     if (x % a.om < a.nm[x / a.om]) base = max(base, (int64_t)a.mfree[x]);
   for (int r = threadIdx.x; r < a.nr; r += blockDim.x) base = max(base, (int64_t)a.running[2 * r]);
+  for (int r = threadIdx.x; r < a.nf; r += blockDim.x) {
+    const int st = a.fixed[3 * r], end = a.fixed[3 * r + 1], q = a.fixed[3 * r + 2];
+    if (st < a.rs || end <= st || q < 1 || q > 65535) err |= kErrInval;
+    if (q > a.q_max) err |= kErrInfeasible;
+    base = max(base, (int64_t)end);
+  }
   int64_t tot_base, tot_sum, tot_unfrozen, tot_ops;
   block_reduce_i64(base, sh, true, tot_base);
   block_reduce_i64(sum, sh, false, tot_sum);
@@ -2025,6 +2051,11 @@ struct ReschedArgs {
   int32_t *proc_o, *power_o, *release_o, *due_o, *first_o, *ready_o, *mfree_o, *running_o,
       *active_o;
   int32_t running_cap;  // pairs of room in running_o
+  // the traditional static approach: every known job frozen whole, its ops not
+  // started by rs kept in place (fixed_o, room for fixed_cap triples)
+  int32_t static_mode;
+  int32_t *fixed_o;
+  int32_t fixed_cap;
 };
 
 // Predictive-reactive rescheduling (Section 4.1) in one block of 1024
@@ -2032,8 +2063,8 @@ struct ReschedArgs {
 // (S < rs < S + P, Algorithm 1) keeps its machine and power until it ends.
 __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header *h) {
   __shared__ int64_t sh[1024];
-  __shared__ int scan_run[1024], scan_act[1024];
-  __shared__ int carry_run, carry_act;
+  __shared__ int scan_run[1024], scan_act[1024], scan_fix[1024];
+  __shared__ int carry_run, carry_act, carry_fix;
   const int t = threadIdx.x, T = blockDim.x;
   const int g = a.g, om = a.om, n = a.n0 + a.n_new;
   const size_t row = (size_t)g * om;
@@ -2057,14 +2088,41 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
   if (t == 0) {
     carry_run = 0;
     carry_act = 0;
+    carry_fix = 0;
   }
   __syncthreads();
   int err = 0;
   int64_t tard = 0, cmax = 0;
   for (int b0 = 0; b0 < n; b0 += T) {
     const int j = b0 + t;
-    int run = 0, act = 0, run_end = 0, run_q = 0;
-    if (j < a.n0) {
+    int run = 0, act = 0, run_end = 0, run_q = 0, nfix = 0;
+    if (j < a.n0 && a.static_mode) {
+      // Static approach: the job's whole plan stays; each stage's planned
+      // completion (kept in column 0 of machine_free) bounds the arrivals.
+      int last_end = a.release[j];
+      for (int s = 0; s < g; ++s) {
+        const int m = a.plan_mach[(size_t)j * g + s], st = a.plan_start[(size_t)j * g + s];
+        if (m < 0 || m >= a.nm[s] || st < 0) {
+          err |= kErrInval;
+          break;
+        }
+        const int end = st + a.proc[((size_t)j * g + s) * om + m];
+        atomicMax(&a.mfree_o[s * om], end);
+        if (st < a.rs && end > a.rs) {
+          err |= run ? kErrInval : 0;  // two ops of one job running at once
+          run = 1;
+          run_end = end;
+          run_q = a.power[((size_t)j * g + s) * om + m];
+        } else if (st >= a.rs) {
+          ++nfix;
+        }
+        last_end = end;
+      }
+      a.first_o[j] = g;
+      a.ready_o[j] = last_end;
+      tard += max(last_end - a.due[j], 0);
+      cmax = max(cmax, (int64_t)last_end);
+    } else if (j < a.n0) {
       int f = g;
       for (int s = 0; s < g; ++s)
         if (a.plan_start[(size_t)j * g + s] >= a.rs) {
@@ -2102,16 +2160,34 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
       a.ready_o[j] = a.new_release[j - a.n0];
       act = 1;
     }
-    // ordered compaction of running ops and active jobs (ascending job id)
+    // ordered compaction of running ops, fixed ops and active jobs (ascending job id)
     scan_run[t] = run;
     scan_act[t] = act;
+    scan_fix[t] = nfix;
     __syncthreads();
     for (int d = 1; d < T; d <<= 1) {
       const int vr = t >= d ? scan_run[t - d] : 0, va = t >= d ? scan_act[t - d] : 0;
+      const int vf = t >= d ? scan_fix[t - d] : 0;
       __syncthreads();
       scan_run[t] += vr;
       scan_act[t] += va;
+      scan_fix[t] += vf;
       __syncthreads();
+    }
+    if (nfix) {
+      int pos = carry_fix + scan_fix[t] - nfix;
+      for (int s = 0; s < g; ++s) {
+        const int m = a.plan_mach[(size_t)j * g + s], st = a.plan_start[(size_t)j * g + s];
+        if (st < a.rs) continue;
+        if (pos >= a.fixed_cap) {
+          err |= kErrInval;
+          break;
+        }
+        a.fixed_o[3 * pos] = st;
+        a.fixed_o[3 * pos + 1] = st + a.proc[((size_t)j * g + s) * om + m];
+        a.fixed_o[3 * pos + 2] = a.power[((size_t)j * g + s) * om + m];
+        ++pos;
+      }
     }
     if (run) {
       const int pos = carry_run + scan_run[t] - 1;
@@ -2127,9 +2203,13 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
     if (t == T - 1) {
       carry_run += scan_run[t];
       carry_act += scan_act[t];
+      carry_fix += scan_fix[t];
     }
     __syncthreads();
   }
+  if (a.static_mode)  // every machine of a stage is free from the stage's planned completion
+    for (int x = t; x < g * om; x += T)
+      if (x % om) a.mfree_o[x] = x % om < a.nm[x / om] ? a.mfree_o[x - x % om] : 0;
   int64_t tot_tard, tot_cmax;
   block_reduce_i64(tard, sh, false, tot_tard);
   block_reduce_i64(cmax, sh, true, tot_cmax);
@@ -2139,11 +2219,13 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
     h->frozen_cmax = (int32_t)tot_cmax;
     h->n_running = carry_run;
     h->n_active = carry_act;
+    h->n_fixed = a.static_mode ? min(carry_fix, a.fixed_cap) : 0;
   }
   __threadfence_block();
   __syncthreads();
   PrepArgs p{a.nm, a.proc_o, a.power_o, a.first_o, a.ready_o, a.mfree_o, a.running_o, a.active_o,
-             n, g, om, a.q_max, a.rs, min(carry_run, a.running_cap), carry_act};
+             n, g, om, a.q_max, a.rs, min(carry_run, a.running_cap), carry_act,
+             a.static_mode ? a.fixed_o : nullptr, a.static_mode ? min(carry_fix, a.fixed_cap) : 0};
   prepare_body(p, h);
 }
 
@@ -2208,13 +2290,14 @@ int omp_of(int om) { return om <= 4 ? 4 : om <= 8 ? 8 : 16; }
 int check_host(const ffs_instance *in) {
   if (!in) return FFS_E_INVAL;
   if (in->n_stages < 1 || in->o_max < 1 || in->n_jobs < 0 || in->n_active < 0 ||
-      in->n_active > in->n_jobs || in->n_running < 0 || in->q_max < 1)
+      in->n_active > in->n_jobs || in->n_running < 0 || in->q_max < 1 || in->n_fixed < 0)
     return FFS_E_INVAL;
   if (in->o_max > 16 || in->n_stages > kMaxStages || in->n_jobs >= (1 << 20) || in->q_max > 255 ||
       in->n_active > kMaxGenes || in->rs < 0 || in->rs >= kMaxTime)
     return FFS_E_UNSUPPORTED;
   if (!in->n_machines || !in->proc || !in->power || !in->due || !in->first_stage || !in->ready ||
-      !in->machine_free || (in->n_running && !in->running) || (in->n_active && !in->active))
+      !in->machine_free || (in->n_running && !in->running) || (in->n_active && !in->active) ||
+      (in->n_fixed && !in->fixed))
     return FFS_E_INVAL;
   return FFS_OK;
 }
@@ -2238,6 +2321,8 @@ DInst make_dinst(const ffs_instance *in, const uint32_t *pq) {
   d.wt = in->wt;
   d.rs = in->rs;
   d.nr = in->n_running;
+  d.fixed = in->fixed;
+  d.nf = in->n_fixed;
   d.n = in->n_active;
   d.frozen_cmax = in->frozen_cmax;
   d.horizon = in->horizon;
@@ -2864,6 +2949,57 @@ int static_scratch(void **out) {
   return FFS_OK;
 }
 
+// Body of reschedule and reschedule_static.
+int reschedule_any(const ffs_instance *prev, const int32_t *plan_start, const int32_t *plan_mach,
+                   int32_t rs, int32_t n_new, const int32_t *new_proc, const int32_t *new_power,
+                   const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
+                   void *workspace, size_t workspace_bytes, hipStream_t s, bool static_mode) {
+  int rc = check_host(prev);
+  if (rc) return rc;
+  if (!next || rs < prev->rs || n_new < 0 || (prev->n_jobs > 0 && (!plan_start || !plan_mach)) ||
+      (n_new > 0 && (!new_proc || !new_power || !new_release || !new_due)) || !prev->release)
+    return FFS_E_INVAL;
+  if (prev->n_jobs + (int64_t)n_new >= (1 << 20) || rs >= kMaxTime) return FFS_E_UNSUPPORTED;
+  if (!next->proc || !next->power || !next->release || !next->due || !next->first_stage ||
+      !next->ready || !next->machine_free || !next->running || !next->active ||
+      (static_mode && prev->n_jobs > 0 && !next->fixed))
+    return FFS_E_INVAL;
+  if (!workspace || workspace_bytes < ffs_reschedule_workspace_size(prev->n_jobs, n_new))
+    return FFS_E_WORKSPACE;
+  Header *h = (Header *)workspace;
+  if ((rc = clear_header(h, s))) return rc;
+  ReschedArgs a{prev->n_machines, prev->proc, prev->power, prev->release, prev->due,
+                prev->n_jobs, prev->n_stages, prev->o_max, prev->q_max, prev->rs,
+                plan_start, plan_mach, rs, n_new, new_proc, new_power, new_release, new_due,
+                (int32_t *)next->proc, (int32_t *)next->power, (int32_t *)next->release,
+                (int32_t *)next->due, (int32_t *)next->first_stage, (int32_t *)next->ready,
+                (int32_t *)next->machine_free, (int32_t *)next->running, (int32_t *)next->active,
+                prev->n_stages * prev->o_max, static_mode ? 1 : 0,
+                static_mode ? (int32_t *)next->fixed : nullptr, prev->n_jobs * prev->n_stages};
+  if (launch(-1, reschedule_kernel, dim3(1), dim3(1024), 0, s, a, h) != hipSuccess)
+    return FFS_E_DEVICE;
+  Header host;
+  if ((rc = read_header(h, &host, s))) return rc;
+  if ((rc = err_code(host.err))) return rc;
+  if (host.horizon + (int64_t)rs >= kMaxTime) return FFS_E_UNSUPPORTED;
+  next->n_jobs = prev->n_jobs + n_new;
+  next->n_stages = prev->n_stages;
+  next->o_max = prev->o_max;
+  if (!next->n_machines) next->n_machines = prev->n_machines;
+  next->q_max = prev->q_max;
+  next->wt = prev->wt;
+  next->rs = rs;
+  next->n_running = host.n_running;
+  next->n_fixed = static_mode ? host.n_fixed : 0;
+  next->frozen_tardiness = host.frozen_tardiness;
+  next->frozen_cmax = host.frozen_cmax;
+  next->n_active = host.n_active;
+  next->horizon = (int32_t)host.horizon;
+  next->n_ops = host.n_ops;
+  next->decode_rules = prev->decode_rules;
+  return check_host(next);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2897,7 +3033,8 @@ int ffs_prepare(ffs_instance *inst, void *workspace, size_t workspace_bytes, voi
   if ((rc = clear_header(h, s))) return rc;
   PrepArgs a{inst->n_machines, inst->proc, inst->power, inst->first_stage, inst->ready,
              inst->machine_free, inst->running, inst->active, inst->n_jobs, inst->n_stages,
-             inst->o_max, inst->q_max, inst->rs, inst->n_running, inst->n_active};
+             inst->o_max, inst->q_max, inst->rs, inst->n_running, inst->n_active, inst->fixed,
+             inst->n_fixed};
   if (launch(-1, prepare_kernel, dim3(1), dim3(1024), 0, s, a, h) != hipSuccess) return FFS_E_DEVICE;
   Header host;
   if ((rc = read_header(h, &host, s))) return rc;
@@ -3131,48 +3268,17 @@ int reschedule(const ffs_instance *prev, const int32_t *plan_start, const int32_
                int32_t rs, int32_t n_new, const int32_t *new_proc, const int32_t *new_power,
                const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
                void *workspace, size_t workspace_bytes, void *stream) {
-  int rc = check_host(prev);
-  if (rc) return rc;
-  if (!next || rs < prev->rs || n_new < 0 || (prev->n_jobs > 0 && (!plan_start || !plan_mach)) ||
-      (n_new > 0 && (!new_proc || !new_power || !new_release || !new_due)) || !prev->release)
-    return FFS_E_INVAL;
-  if (prev->n_jobs + (int64_t)n_new >= (1 << 20) || rs >= kMaxTime) return FFS_E_UNSUPPORTED;
-  if (!next->proc || !next->power || !next->release || !next->due || !next->first_stage ||
-      !next->ready || !next->machine_free || !next->running || !next->active)
-    return FFS_E_INVAL;
-  if (!workspace || workspace_bytes < ffs_reschedule_workspace_size(prev->n_jobs, n_new))
-    return FFS_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  Header *h = (Header *)workspace;
-  if ((rc = clear_header(h, s))) return rc;
-  ReschedArgs a{prev->n_machines, prev->proc, prev->power, prev->release, prev->due,
-                prev->n_jobs, prev->n_stages, prev->o_max, prev->q_max, prev->rs,
-                plan_start, plan_mach, rs, n_new, new_proc, new_power, new_release, new_due,
-                (int32_t *)next->proc, (int32_t *)next->power, (int32_t *)next->release,
-                (int32_t *)next->due, (int32_t *)next->first_stage, (int32_t *)next->ready,
-                (int32_t *)next->machine_free, (int32_t *)next->running, (int32_t *)next->active,
-                prev->n_stages * prev->o_max};
-  if (launch(-1, reschedule_kernel, dim3(1), dim3(1024), 0, s, a, h) != hipSuccess)
-    return FFS_E_DEVICE;
-  Header host;
-  if ((rc = read_header(h, &host, s))) return rc;
-  if ((rc = err_code(host.err))) return rc;
-  if (host.horizon + (int64_t)rs >= kMaxTime) return FFS_E_UNSUPPORTED;
-  next->n_jobs = prev->n_jobs + n_new;
-  next->n_stages = prev->n_stages;
-  next->o_max = prev->o_max;
-  if (!next->n_machines) next->n_machines = prev->n_machines;
-  next->q_max = prev->q_max;
-  next->wt = prev->wt;
-  next->rs = rs;
-  next->n_running = host.n_running;
-  next->frozen_tardiness = host.frozen_tardiness;
-  next->frozen_cmax = host.frozen_cmax;
-  next->n_active = host.n_active;
-  next->horizon = (int32_t)host.horizon;
-  next->n_ops = host.n_ops;
-  next->decode_rules = prev->decode_rules;
-  return check_host(next);
+  return reschedule_any(prev, plan_start, plan_mach, rs, n_new, new_proc, new_power, new_release,
+                        new_due, next, workspace, workspace_bytes, (hipStream_t)stream, false);
+}
+
+int reschedule_static(const ffs_instance *prev, const int32_t *plan_start,
+                      const int32_t *plan_mach, int32_t rs, int32_t n_new,
+                      const int32_t *new_proc, const int32_t *new_power,
+                      const int32_t *new_release, const int32_t *new_due, ffs_instance *next,
+                      void *workspace, size_t workspace_bytes, void *stream) {
+  return reschedule_any(prev, plan_start, plan_mach, rs, n_new, new_proc, new_power, new_release,
+                        new_due, next, workspace, workspace_bytes, (hipStream_t)stream, true);
 }
 
 size_t ffs_batch_workspace_size(const ffs_batch_params *params) {

@@ -47,6 +47,7 @@ class FfsInstance(ctypes.Structure):
         ("frozen_tardiness", ctypes.c_int64), ("frozen_cmax", ctypes.c_int32),
         ("n_active", ctypes.c_int32), ("active", _vp),
         ("horizon", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("decode_rules", ctypes.c_int32),
+        ("n_fixed", ctypes.c_int32), ("fixed", _vp),
     ]
 
 
@@ -101,6 +102,7 @@ _lib.ffs_reschedule_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
 _lib.ffs_reschedule_workspace_size.restype = ctypes.c_size_t
 _lib.reschedule.argtypes = [_P(FfsInstance), _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                             _vp, _vp, _P(FfsInstance), _vp, ctypes.c_size_t, _vp]
+_lib.reschedule_static.argtypes = _lib.reschedule.argtypes
 _lib.ffs_timing_enable.argtypes = [ctypes.c_int32]
 _lib.ffs_timing_every.argtypes = [ctypes.c_int32]
 _lib.ffs_timing_read.argtypes = [ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64)]
@@ -109,7 +111,8 @@ _lib.ffs_strerror.restype = ctypes.c_char_p
 _lib.ffs_build_id.argtypes = []
 _lib.ffs_build_id.restype = ctypes.c_char_p
 for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_noalloc", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
-           "reschedule", "ffs_timing_enable", "ffs_timing_every", "ffs_timing_read"):
+           "reschedule", "reschedule_static", "ffs_timing_enable", "ffs_timing_every",
+           "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -166,6 +169,8 @@ class DeviceInstance:
             "machine_free": _i32(np.asarray(inst.machine_free).reshape(g, om), device),
             "running": _i32(np.asarray(inst.running).reshape(-1, 2), device),
             "active": _i32(inst.active, device),
+            "fixed": _i32(np.asarray(getattr(inst, "fixed", np.zeros((0, 3)))).reshape(-1, 3),
+                          device),
         }
         s = FfsInstance(
             n, g, om, _dptr(t["n_machines"]), _dptr(t["proc"]), _dptr(t["power"]),
@@ -173,7 +178,8 @@ class DeviceInstance:
             _dptr(t["first_stage"]), _dptr(t["ready"]), _dptr(t["machine_free"]),
             int(len(inst.running)), _dptr(t["running"]), int(inst.frozen_tardiness),
             int(inst.frozen_cmax), int(len(inst.active)), _dptr(t["active"]), 0, 0,
-            int(getattr(inst, "decode_rules", 0)))
+            int(getattr(inst, "decode_rules", 0)), int(t["fixed"].shape[0]),
+            _dptr(t["fixed"]) if t["fixed"].numel() else None)
         d = cls(s, t)
         if prepare:
             d.prepare(workspace)
@@ -204,6 +210,7 @@ class DeviceInstance:
         out = {k: v.cpu().numpy() for k, v in self.t.items() if not k.startswith("_")}
         out["running"] = out["running"][:s.n_running].reshape(-1, 2)
         out["active"] = out["active"][:s.n_active]
+        out["fixed"] = out["fixed"].reshape(-1, 3)[:s.n_fixed]
         for k in ("n_jobs", "n_stages", "o_max", "q_max", "wt", "rs", "frozen_tardiness",
                   "frozen_cmax", "horizon", "n_ops", "decode_rules"):
             out[k] = int(getattr(s, k))
@@ -370,8 +377,9 @@ class GA:
 
 
 def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.Tensor, arrival,
-               workspace=None) -> DeviceInstance:
-    """Freeze `prev`'s executed plan at arrival.rs, append the arrival's jobs."""
+               workspace=None, static=False) -> DeviceInstance:
+    """Freeze `prev`'s executed plan at arrival.rs, append the arrival's jobs.
+    static=True: the traditional static approach (reschedule_static)."""
     s = prev.s
     dev = prev.t["proc"].device
     g, om = int(s.n_stages), int(s.o_max)
@@ -388,10 +396,11 @@ def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.
         "machine_free": torch.empty((g, om), dtype=torch.int32, device=dev),
         "running": torch.empty((max(g * om, 1), 2), dtype=torch.int32, device=dev),
         "active": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+        "fixed": torch.empty((max(int(s.n_jobs) * g, 1), 3), dtype=torch.int32, device=dev),
     }
     nxt = FfsInstance()
     for k in ("n_machines", "proc", "power", "release", "due", "first_stage", "ready",
-              "machine_free", "running", "active"):
+              "machine_free", "running", "active", "fixed"):
         setattr(nxt, k, t[k].data_ptr())
     new = {
         "proc": _i32(np.asarray(arrival.proc).reshape(n_new, g, om), dev),
@@ -403,10 +412,11 @@ def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.
         need, dtype=torch.uint8, device=dev)
     ps = plan_start.to(device=dev, dtype=torch.int32).contiguous()
     pm = plan_mach.to(device=dev, dtype=torch.int32).contiguous()
-    _check(_lib.reschedule(ctypes.byref(s), _dptr(ps), _dptr(pm), int(arrival.rs), n_new,
-                           _dptr(new["proc"]), _dptr(new["power"]), _dptr(new["release"]),
-                           _dptr(new["due"]), ctypes.byref(nxt), _dptr(ws), ws.numel(),
-                           _stream()), "reschedule")
+    fn = _lib.reschedule_static if static else _lib.reschedule
+    _check(fn(ctypes.byref(s), _dptr(ps), _dptr(pm), int(arrival.rs), n_new,
+              _dptr(new["proc"]), _dptr(new["power"]), _dptr(new["release"]),
+              _dptr(new["due"]), ctypes.byref(nxt), _dptr(ws), ws.numel(), _stream()),
+           "reschedule_static" if static else "reschedule")
     t["_new"] = new
     return DeviceInstance(nxt, t)
 
@@ -433,7 +443,8 @@ def exported_symbols():
                  "ffs_decode_xy",
                  "ffs_status",
                  "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
-                 "ffs_reschedule_workspace_size", "reschedule", "ffs_timing_enable",
+                 "ffs_reschedule_workspace_size", "reschedule", "reschedule_static",
+                 "ffs_timing_enable",
                  "ffs_timing_every", "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",
                  "ga_batch_create", "ga_batch_set", "ga_batch_clear", "ga_batch_step",
                  "ga_batch_best", "ga_batch_view", "ga_batch_destroy", "sg_refresh",

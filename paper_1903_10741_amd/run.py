@@ -43,13 +43,17 @@ class EventLoop:
     """The events of a workload run one at a time, in order: event e's GA (init +
     `generations`), the decode of its best plan into the executed plan, and the
     rescheduling at arrival e. After the last event the loop starts again at
-    event 0 from the initial instance, which stays resident on the device."""
+    event 0 from the initial instance, which stays resident on the device.
+    static=True handles every arrival by the traditional static approach
+    (reschedule_static) instead of complete rescheduling."""
 
-    def __init__(self, wl, device="cuda", generations=None, lds_slots=0, keep_instances=False):
+    def __init__(self, wl, device="cuda", generations=None, lds_slots=0, keep_instances=False,
+                 static=False):
         self.wl = wl
         self.gens = wl.generations if generations is None else generations
         self.cfg = ffsga.GaConfig.of(wl.ga, lds_slots=lds_slots)
         self.keep_instances = keep_instances
+        self.static = static
         g = int(wl.initial.n_stages)
         n_final = int(wl.initial.n_jobs) + sum(len(a.release) for a in wl.arrivals)
         self.plan_s = torch.full((n_final, g), -1, dtype=torch.int32, device=device)
@@ -81,7 +85,8 @@ class EventLoop:
         if self.keep_instances:
             ev.instance = d
         if e + 1 < self.n_events:
-            self.dinst = ffsga.reschedule(d, self.plan_s[:n], self.plan_m[:n], self.wl.arrivals[e])
+            self.dinst = ffsga.reschedule(d, self.plan_s[:n], self.plan_m[:n], self.wl.arrivals[e],
+                                          static=self.static)
             self.event = e + 1
         else:
             self.event = 0
@@ -89,9 +94,9 @@ class EventLoop:
 
 
 def run_workload(wl, device="cuda", generations=None, lds_slots=0, keep_instances=False,
-                 sync_results=True, keep_work=False) -> RunResult:
+                 sync_results=True, keep_work=False, static=False) -> RunResult:
     """Run every event of workload `wl` on the device. Returns per-event best objectives."""
-    loop = EventLoop(wl, device, generations, lds_slots, keep_instances)
+    loop = EventLoop(wl, device, generations, lds_slots, keep_instances, static)
     res = RunResult()
     for _ in range(loop.n_events):
         ev = loop.run_event()

@@ -48,6 +48,8 @@ class Instance:
     frozen_cmax: int
     active: np.ndarray       # int32 [n_active]
     decode_rules: int = 0    # job-vector decode variants: 1 FIFO stage order, 2 power-aware ECT
+    fixed: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    # int32 [n_fixed, 3] (start, end, q): planned ops kept in place (static approach)
 
     @property
     def n_active(self) -> int:
@@ -215,6 +217,24 @@ def table5_instance(seed: int, n_jobs: int = 10, n_stages: int = 3, machines: in
     nm = np.full(n_stages, machines, np.int32)
     power = np.ones((n_jobs, n_stages, machines), np.int32)
     return initial_instance(proc, power, release, due, nm, q_max, 100)
+
+
+def table5_arrival(seed: int, inst: Instance, rs: int, n_new: int) -> Arrival:
+    """New jobs for a Table 5-shaped instance: the instance's stage times (the same
+    for every job) and unit power, release RS, D = RS + P-bar * (1 + sigma) with
+    sigma ~ U[0, 2], rounded."""
+    rng = np.random.default_rng(seed)
+    g, om = int(inst.n_stages), int(inst.o_max)
+    p_sm = np.asarray(inst.proc)[0]
+    proc = np.repeat(p_sm[None], n_new, axis=0).astype(np.int32)
+    p_bar = float(sum(p_sm[s, :int(inst.n_machines[s])].mean() for s in range(g)))
+    sigma = rng.uniform(0, 2, size=n_new)
+    due = (rs + round_half_up(p_bar * (1 + sigma))).astype(np.int32)
+    return Arrival(int(rs), proc, np.ones((n_new, g, om), np.int32), np.full(n_new, rs, np.int32),
+                   due)
+
+
+TABLE5_GA = GaParams(64, 8, 8)   # 64 x 64 = 4096 individuals in 8 x 8 islands (Section 5.1)
 
 
 def config2(seed: int = 0, generations: int = 500) -> Workload:

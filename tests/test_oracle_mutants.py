@@ -19,7 +19,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "ffs_oracle.c")
 PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_init_work.py", "tests/test_oracle_xy.py",
-        "tests/test_oracle_rules.py"]
+        "tests/test_oracle_rules.py", "tests/test_oracle_static.py"]
 
 # (name, text in ffs_oracle.c (must occur once), replacement)
 MUTANTS = [
@@ -62,6 +62,14 @@ MUTANTS = [
      "out->ready[j] = prev->release[j];"),
     ("frozen machine free time dropped",
      "if (end > out->machine_free[s * om + m]) out->machine_free[s * om + m] = end;", ";"),
+    # the traditional static approach (Fig. 7)
+    ("static: arrivals after each machine's last op, not the stage's",
+     "out->machine_free[s * om + m] = m < prev->n_machines[s] ? stage_end[s] : 0;",
+     "out->machine_free[s * om + m] = 0;"),
+    ("static: unstarted planned ops hold no power",
+     "      d->profile[tau] += q;\n  }\n  return ORC_OK;", "      ;\n  }\n  return ORC_OK;"),
+    ("static: op running at RS dropped", "if (st < rs && end > rs) {  /* running at RS",
+     "if (0) {  /* running at RS"),
     # random numbers and initialisation
     ("Philox key schedule", "k0 += W0;", "k0 += W1;"),
     ("Sattolo shuffle", "int32_t r = (int32_t)draw_below(w[d % 4], (uint32_t)(pos + 1));",
