@@ -364,8 +364,10 @@ def bench_rs_ratio(args):
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
+    import dataclasses
     gens = args.generations or 100
-    ga = W.TABLE5_GA
+    xy = args.encoding == "xy"
+    ga = dataclasses.replace(W.TABLE5_GA, encoding=1 if xy else 0)
     cfg = ffsga.GaConfig.of(ga)
     paper = {0.2: (2727.61, 1195.29, 2.28), 0.4: (5608.31, 3745.06, 1.50),
              0.6: (5464.86, 4673.57, 1.17), 0.8: (4805.43, 4755.91, 1.01)}
@@ -380,7 +382,7 @@ def bench_rs_ratio(args):
             g0 = ffsga.GA(d0, cfg, sd, 0, 0)
             g0.step(gens)
             prio, _ = g0.best()
-            plan = ffsga.ffs_decode(d0, prio.view(1, -1), want_schedule=True)
+            plan = ffsga.ffs_decode(d0, prio.view(1, -1), want_schedule=True, xy=xy)
             ps, pm = plan["start"][0], plan["mach"][0]
             p_np = np.asarray(inst.proc)
             s_np, m_np = ps.cpu().numpy(), pm.cpu().numpy()
@@ -416,8 +418,66 @@ def bench_rs_ratio(args):
                      "workload": f"Table 5-shaped instances {args.seed}-"
                                  f"{args.seed + args.instances - 1} (10 jobs, 3 stages x 2 machines, "
                                  f"Q_max 4, WT 100); GA 64 islands x 8x8, {gens} generations per "
-                                 f"event; arrivals of round(r x 10) jobs at RS = r x makespan",
+                                 f"event; arrivals of round(r x 10) jobs at RS = r x makespan; "
+                                 f"{'X/Y chromosomes' if xy else 'job-priority vectors'}",
+                     "encoding": "xy" if xy else "job priority vector",
                      "decodes": decodes, "table": rows})
+    out["steps"] = 1
+    out["warmup"] = 0
+    return out
+
+
+def bench_schemes(args):
+    """Section 5.2, Tables 8-9: the hybrid GA (8x8 islands, ring migration) against
+    the classical GA (roulette wheel on eq. (13), random pairing) and the cellular
+    GA (neighbourhood parents, replace if better), all on the GPU, on Table
+    5-shaped instances (10 jobs, 3 stages of 2 machines, power peak 4, WT = 100)
+    at populations 64x64, 128x128 and 256x256, 100 generations from the same
+    seed: best objective (mean and best over the instances) and wall time per
+    100 generations (init included)."""
+    import numpy as np
+    import torch
+    from paper_1903_10741_amd import ffsga
+    from paper_1903_10741_amd import workloads as W
+    gens = args.generations or 100
+    paper_s = {64: (8.77, 8.14, 129.16), 128: (30.71, 31.13, 554.01), 256: (105.73, 108.07, 2651.61)}
+    rows = []
+    for side in (64, 128, 256):
+        per = {}
+        for name, scheme, gp in (("hybrid", ffsga.FFS_GA_HYBRID, W.GaParams(side * side // 64, 8, 8)),
+                                 ("classical", ffsga.FFS_GA_CLASSICAL, W.GaParams(1, side, side)),
+                                 ("cellular", ffsga.FFS_GA_CELLULAR, W.GaParams(1, side, side))):
+            cfg = ffsga.GaConfig.of(gp, scheme=scheme)
+            objs, times = [], []
+            for sd in range(args.seed, args.seed + args.instances):
+                d = ffsga.DeviceInstance.from_host(W.table5_instance(sd))
+                if sd == args.seed:   # warm-up of this launch shape
+                    ffsga.GA(d, cfg, sd, 0, 0).step(2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = ffsga.GA(d, cfg, sd, 0, 0)
+                g.step(gens)
+                best = int(g.best()[1].item())
+                times.append(time.perf_counter() - t0)
+                objs.append(best)
+            per[name] = {"mean_best_obj": float(np.mean(objs)), "best_obj": int(min(objs)),
+                         "s_per_100_generations": float(np.mean(times)) * 100 / gens,
+                         "decodes_per_s": (1 + gens) * gp.pop / float(np.mean(times))}
+            progress(f"{side}x{side} {name}: mean best {np.mean(objs):.1f}, "
+                     f"{np.mean(times) * 1e3:.1f} ms per run")
+        rows.append({"population": f"{side}x{side}", **per,
+                     "paper_k40_s_per_100_generations": {"hybrid": paper_s[side][0],
+                                                         "cellular": paper_s[side][1],
+                                                         "classical_1_cpu_core": paper_s[side][2]}})
+    out = common(args, "wall time per 100 generations, hybrid vs classical vs cellular GA",
+                 rows[0]["hybrid"]["s_per_100_generations"], "s (hybrid GA, 64x64)",
+                 sum(r[k]["s_per_100_generations"] for r in rows
+                     for k in ("hybrid", "classical", "cellular")) * 1e3, "int32", {
+                     "workload": f"Table 5-shaped instances {args.seed}-"
+                                 f"{args.seed + args.instances - 1} (10 jobs, 3 stages x 2 machines, "
+                                 f"Q_max 4, WT 100), {gens} generations per run",
+                     "table": rows})
+    out["higher_is_better"] = False
     out["steps"] = 1
     out["warmup"] = 0
     return out
@@ -651,7 +711,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "paper", "batch", "serve", "surrogate", "rs-ratio"],
+                    choices=["large", "paper", "batch", "serve", "surrogate", "rs-ratio",
+                             "schemes"],
                     help="large (default): the large-200x10x4-6 event loop, one event per step, "
                          "with the paper-shaped workload measured beside it")
     ap.add_argument("--lds-slots", type=int, default=0)
@@ -678,7 +739,7 @@ def main():
     ap.add_argument("--gens-per-tick", type=int, default=10)
     ap.add_argument("--race-seeds", type=int, default=10)
     ap.add_argument("--instances", type=int, default=20,
-                    help="rs-ratio: Table 5-shaped instances per ratio")
+                    help="rs-ratio, schemes: Table 5-shaped instances per point")
     ap.add_argument("--train-instances", type=int, default=100)
     ap.add_argument("--train-seeds", type=int, default=3,
                     help="surrogate: own-instance networks per instance (initial weights and "
@@ -712,6 +773,9 @@ def main():
         return
     if args.workload == "rs-ratio":
         print(json.dumps(bench_rs_ratio(args)), flush=True)
+        return
+    if args.workload == "schemes":
+        print(json.dumps(bench_schemes(args)), flush=True)
         return
     if args.workload == "paper":
         out = bench_paper(args, args.steps, args.warmup)

@@ -186,7 +186,34 @@ typedef struct {
                                        1: the paper's X/Y matrices (n_genes = 2 * n_ops, see
                                        ffs_decode_xy). The batched GA and ga_step_screened
                                        take encoding 0 only (else FFS_E_UNSUPPORTED). */
+  int32_t scheme;                   /* FFS_GA_HYBRID (0, the method), or one of the comparison
+                                       GAs of Section 5.2 below */
 } ffs_ga_params;
+
+/* ffs_ga_params.scheme. FFS_GA_CLASSICAL and FFS_GA_CELLULAR are the comparison
+ * GAs of Section 5.2 (Tables 8-9) on job-priority vectors (encoding 0), one
+ * population of rows x cols individuals (islands must be 1; the migration
+ * fields are ignored), generation 0 as the hybrid GA's. Draws: purpose 1
+ * crossover, 2 mutation, as the hybrid GA; 6 the classical GA's roulette.
+ * FFS_GA_CLASSICAL: ga_init also sets E_max of eq. (13), 10^a with the least a
+ *   >= 1 above every objective of generation 0; each generation, slot i's
+ *   parent is the first individual whose running sum of the fitness
+ *   F = max(E_max - obj, 0) (index order) exceeds floor(hi32(w) * sum F /
+ *   2^32), w word 0 of slot i's purpose-6 block (a uniform individual,
+ *   floor(hi32(w) * pop / 2^32), if every fitness is 0) -- the roulette wheel;
+ *   the independent spins make slots (2k, 2k+1) a random pairing: with p_c
+ *   (slot 2k's purpose-1 block) they exchange tails at one cut with
+ *   correction (Fig. 11); a last unpaired slot keeps its parent; swap mutation
+ *   (Fig. 12); replacement as the hybrid GA's over the whole population.
+ * FFS_GA_CELLULAR: cell i takes the best two of itself and its four torus
+ *   neighbours (by objective, then in the order self, up, down, left, right),
+ *   crosses them at its own cut with p_c (the best's head, the second's tail,
+ *   corrected; else a copy of the best), applies the swap mutation, and the
+ *   child replaces the cell only if its objective is strictly lower; the elite
+ *   is the best in history (lowest cell on ties). */
+#define FFS_GA_HYBRID 0
+#define FFS_GA_CLASSICAL 1
+#define FFS_GA_CELLULAR 2
 
 /* ffs_ga_params.lds_slots = FFS_LDS_AUTO (job-priority vectors only; encoding 1
  * gets FFS_E_UNSUPPORTED): ga_init decodes generation 0 with as many on-chip
@@ -225,6 +252,7 @@ typedef struct {
   int64_t *elite_obj;  /* [islands] */
   int64_t *work;       /* [1]: algorithmic work summed over every decode since ga_init
                           (same count as ffs_decode's work output) */
+  int64_t *e_max;      /* [1]: E_max of eq. (13) (FFS_GA_CLASSICAL; 0 otherwise) */
 } ffs_ga_view;
 
 size_t ffs_ga_workspace_size(const ffs_instance *inst, const ffs_ga_params *params);

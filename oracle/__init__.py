@@ -128,9 +128,15 @@ def _load():
                                    ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
                                    ctypes.POINTER(_ReschedOut)]
     lib.orc_reschedule_static.argtypes = lib.orc_reschedule.argtypes
+    lib.orc_emax.argtypes = [_i64p, ctypes.c_int32]
+    lib.orc_emax.restype = ctypes.c_int64
+    lib.orc_ga_generation_scheme.argtypes = [
+        ctypes.POINTER(_Instance), ctypes.POINTER(_GaParams), ctypes.c_int32, ctypes.c_int64,
+        ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, _i32p,
+        _i64p, _i32p, _i64p, _i32p, _i64p, ctypes.c_int32]
     for f in ("orc_decode", "orc_decode_pop", "orc_decode_ops", "orc_ga_init",
               "orc_ga_generation", "orc_ga_breed", "orc_ga_finish", "orc_reschedule",
-              "orc_reschedule_static",
+              "orc_reschedule_static", "orc_ga_generation_scheme",
               "orc_xy_order", "orc_decode_xy", "orc_decode_xy_pop"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -431,6 +437,58 @@ def ga_run(inst, ga, seed, shop, event, generations, n_threads=1):
     st = ga_init(inst, ga, seed, shop, event, n_threads)
     for k in range(1, generations + 1):
         st = ga_generation(inst, ga, seed, shop, event, k, st, n_threads=n_threads)
+    return st
+
+
+GA_CLASSICAL = 1   # the classical GA of Section 5.2 (roulette wheel, random pairing)
+GA_CELLULAR = 2    # the cellular GA of Section 5.2 (neighbourhood parents, replace if better)
+
+
+def emax(obj):
+    """E_max of eq. (13): 10^a, the least a >= 1 with every objective below it."""
+    o = _arr(obj, np.int64)
+    return int(_load().orc_emax(_ptr(o, _i64p), int(o.size)))
+
+
+def ga_generation_scheme(inst, ga, scheme, e_max, seed, shop, event, gen, state, n_threads=1):
+    """One generation of the classical (GA_CLASSICAL) or cellular (GA_CELLULAR) GA
+    on job-priority vectors (one population, ga.islands == 1). Returns a new state."""
+    lib = _load()
+    p = _Pinned(inst)
+    gp = _gp(ga)
+    pop = gp.rows * gp.cols
+    n = max(p.n_active, 1)
+    prio_in = _arr(state["prio"]).reshape(pop, -1)
+    if prio_in.shape[1] == 0:
+        prio_in = np.zeros((pop, 1), np.int32)
+    elite_in = _arr(state["elite"]).reshape(1, -1)
+    if elite_in.shape[1] == 0:
+        elite_in = np.zeros((1, 1), np.int32)
+    obj_in = _arr(state["obj"], np.int64)
+    eobj_in = _arr(state["elite_obj"], np.int64)
+    prio = np.zeros((pop, n), np.int32)
+    obj = np.zeros(pop, np.int64)
+    elite = np.zeros((1, n), np.int32)
+    eobj = np.zeros(1, np.int64)
+    rc = lib.orc_ga_generation_scheme(p.ref(), ctypes.byref(gp), int(scheme), int(e_max), seed,
+                                      shop, event, gen, _ptr(prio_in), _ptr(obj_in, _i64p),
+                                      _ptr(elite_in), _ptr(eobj_in, _i64p), _ptr(prio),
+                                      _ptr(obj, _i64p), _ptr(elite), _ptr(eobj, _i64p),
+                                      int(n_threads))
+    _check(rc, "orc_ga_generation_scheme")
+    L = p.n_active
+    return {"prio": prio[:, :L].copy(), "obj": obj, "elite": elite[:, :L].copy(),
+            "elite_obj": eobj}
+
+
+def ga_run_scheme(inst, ga, scheme, seed, shop, event, generations, n_threads=1):
+    """Generation 0 (ga_init) and `generations` generations of a comparison GA;
+    the state carries e_max (eq. (13), from generation 0)."""
+    st = ga_init(inst, ga, seed, shop, event, n_threads)
+    e = emax(st["obj"])
+    for g in range(1, generations + 1):
+        st = ga_generation_scheme(inst, ga, scheme, e, seed, shop, event, g, st, n_threads)
+    st["e_max"] = e
     return st
 
 

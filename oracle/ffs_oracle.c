@@ -890,6 +890,143 @@ int orc_ga_finish(const orc_instance *in, const orc_ga_params *gp, int32_t gen,
 /* ------------------------------------------------------------------------ */
 /* Predictive-reactive complete rescheduling (Section 4.1, eq. (10))         */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* The comparison GAs of Section 5.2 (classical and cellular)                */
+/* ------------------------------------------------------------------------ */
+int64_t orc_emax(const int64_t *obj, int32_t pop) {
+  int64_t e = 10;
+  for (;;) {
+    int below = 1;
+    for (int32_t i = 0; i < pop; ++i)
+      if (obj[i] >= e) below = 0;
+    if (below || e > INT64_MAX / 10) return e;
+    e *= 10;
+  }
+}
+
+/* Roulette spin: the first i with prefix[i] (inclusive running sum of the
+ * fitness, index order) above floor(hi32(w) * total / 2^32). */
+static int32_t roulette(const uint64_t *prefix, int32_t pop, uint64_t total, uint64_t w) {
+  if (total == 0) return (int32_t)draw_below(w, (uint32_t)pop);
+  uint64_t hi, lo;
+  mul_hi_lo((w >> 32) << 32, total, &hi, &lo);
+  for (int32_t i = 0; i < pop; ++i)
+    if (prefix[i] > hi) return i;
+  return pop - 1;  /* unreachable: hi < total = prefix[pop - 1] */
+}
+
+int orc_ga_generation_scheme(const orc_instance *in, const orc_ga_params *gp, int32_t scheme,
+                             int64_t e_max, uint64_t seed, uint64_t shop, int32_t event,
+                             int32_t gen, const int32_t *prio_in, const int64_t *obj_in,
+                             const int32_t *elite_in, const int64_t *elite_obj_in,
+                             int32_t *prio_out, int64_t *obj_out, int32_t *elite_out,
+                             int64_t *elite_obj_out, int32_t n_threads) {
+  int rc = check_instance(in);
+  if (rc) return rc;
+  if ((rc = check_ga(in, gp))) return rc;
+  if (gen < 1 || gp->islands != 1 || gp->encoding != 0 ||
+      (scheme != ORC_GA_CLASSICAL && scheme != ORC_GA_CELLULAR))
+    return ORC_E_INVAL;
+  const int32_t n = in->n_active, R = gp->rows, C = gp->cols, pop = R * C;
+  const size_t row = sizeof(int32_t) * (size_t)(n > 0 ? n : 1);
+  int32_t *child = (int32_t *)malloc(row * (size_t)pop);
+  int32_t *tb = (int32_t *)malloc(row);
+  int64_t *cobj = (int64_t *)malloc(sizeof(int64_t) * (size_t)pop);
+  uint64_t *prefix = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)pop);
+  int32_t *par = (int32_t *)malloc(sizeof(int32_t) * (size_t)pop);
+  if (!child || !tb || !cobj || !prefix || !par) {
+    free(child); free(tb); free(cobj); free(prefix); free(par);
+    return ORC_E_NOMEM;
+  }
+  uint64_t w[4];
+  if (scheme == ORC_GA_CLASSICAL) {
+    /* eq. (13) fitness and its running sums, index order */
+    uint64_t total = 0;
+    for (int32_t i = 0; i < pop; ++i) {
+      const int64_t f = e_max - obj_in[i];
+      total += f > 0 ? (uint64_t)f : 0;
+      prefix[i] = total;
+    }
+    for (int32_t i = 0; i < pop; ++i) {
+      rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 6, 0, w);
+      par[i] = roulette(prefix, pop, total, w[0]);
+      memcpy(child + (int64_t)i * n, prio_in + (int64_t)par[i] * n, row);
+    }
+    for (int32_t a = 0; a + 1 < pop && n >= 2; a += 2) {
+      rng_block(seed, shop, (uint64_t)a, (uint64_t)gen, (uint64_t)event, 1, 0, w);
+      if ((uint32_t)(w[0] >> 32) >= gp->pc) continue;
+      const int32_t cut = 1 + (int32_t)draw_below(w[1], (uint32_t)(n - 1));
+      int32_t *ta = (int32_t *)malloc(row);
+      orc_crossover(n, prio_in + (int64_t)par[a] * n, prio_in + (int64_t)par[a + 1] * n, cut, ta, tb);
+      memcpy(child + (int64_t)a * n, ta, row);
+      memcpy(child + (int64_t)(a + 1) * n, tb, row);
+      free(ta);
+    }
+  } else {
+    for (int32_t i = 0; i < pop; ++i) {
+      const int32_t r = i / C, c = i % C;
+      const int32_t cand[5] = {i, ((r - 1 + R) % R) * C + c, ((r + 1) % R) * C + c,
+                               r * C + (c - 1 + C) % C, r * C + (c + 1) % C};
+      /* best two entries by (objective, order) */
+      int32_t b1 = 0, b2 = -1;
+      for (int k = 1; k < 5; ++k)
+        if (obj_in[cand[k]] < obj_in[cand[b1]]) b1 = k;
+      for (int k = 0; k < 5; ++k)
+        if (k != b1 && (b2 < 0 || obj_in[cand[k]] < obj_in[cand[b2]])) b2 = k;
+      const int32_t *p1 = prio_in + (int64_t)cand[b1] * n, *p2 = prio_in + (int64_t)cand[b2] * n;
+      int32_t *v = child + (int64_t)i * n;
+      memcpy(v, p1, row);
+      rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 1, 0, w);
+      if (n >= 2 && (uint32_t)(w[0] >> 32) < gp->pc) {
+        const int32_t cut = 1 + (int32_t)draw_below(w[1], (uint32_t)(n - 1));
+        orc_crossover(n, p1, p2, cut, v, tb);
+      }
+    }
+  }
+  /* swap mutation, as the hybrid GA */
+  for (int32_t i = 0; i < pop; ++i) {
+    rng_block(seed, shop, (uint64_t)i, (uint64_t)gen, (uint64_t)event, 2, 0, w);
+    if ((uint32_t)(w[0] >> 32) < gp->pm && n >= 2) orc_mutate(n, child + (int64_t)i * n, w[1], w[2]);
+  }
+  rc = orc_decode_pop(in, child, pop, cobj, NULL, n_threads);
+  if (rc) {
+    free(child); free(tb); free(cobj); free(prefix); free(par);
+    return rc;
+  }
+  memcpy(elite_out, elite_in, row);
+  elite_obj_out[0] = elite_obj_in[0];
+  if (scheme == ORC_GA_CLASSICAL) {
+    memcpy(prio_out, child, row * (size_t)pop);
+    memcpy(obj_out, cobj, sizeof(int64_t) * (size_t)pop);
+    int32_t b = 0, wst = 0;
+    for (int32_t i = 0; i < pop; ++i) {
+      if (obj_out[i] < obj_out[b]) b = i;
+      if (obj_out[i] > obj_out[wst]) wst = i;
+    }
+    if (obj_out[b] < elite_obj_out[0]) {
+      memcpy(elite_out, prio_out + (int64_t)b * n, row);
+      elite_obj_out[0] = obj_out[b];
+    }
+    memcpy(prio_out + (int64_t)wst * n, elite_out, row);
+    obj_out[wst] = elite_obj_out[0];
+  } else {
+    for (int32_t i = 0; i < pop; ++i) {
+      const int better = cobj[i] < obj_in[i];
+      memcpy(prio_out + (int64_t)i * n, better ? child + (int64_t)i * n : prio_in + (int64_t)i * n, row);
+      obj_out[i] = better ? cobj[i] : obj_in[i];
+    }
+    int32_t b = 0;
+    for (int32_t i = 1; i < pop; ++i)
+      if (obj_out[i] < obj_out[b]) b = i;
+    if (obj_out[b] < elite_obj_out[0]) {
+      memcpy(elite_out, prio_out + (int64_t)b * n, row);
+      elite_obj_out[0] = obj_out[b];
+    }
+  }
+  free(child); free(tb); free(cobj); free(prefix); free(par);
+  return ORC_OK;
+}
+
 int orc_reschedule(const orc_instance *prev, const int32_t *plan_start,
                    const int32_t *plan_mach, int32_t rs, int32_t n_new,
                    const int32_t *new_proc, const int32_t *new_power,

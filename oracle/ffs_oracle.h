@@ -175,6 +175,47 @@ void orc_crossover_xy(int32_t R, const int32_t *a, const int32_t *b, int32_t cut
 void orc_correct(int32_t n, int32_t *v);
 void orc_mutate(int32_t n, int32_t *v, uint64_t w1, uint64_t w2);  /* n >= 2 */
 
+/* The comparison GAs of Section 5.2 (Tables 8-9), on job-priority vectors, one
+ * population of rows x cols individuals (islands must be 1), generation 0 by
+ * orc_ga_init. Draws: purpose 1 crossover, 2 mutation (as the hybrid GA),
+ * 6 the classical GA's roulette spins.
+ *
+ * orc_emax: E_max of eq. (13), 10^a with the least a >= 1 such that every
+ * objective of the initial population is below it (Section 5.1).
+ *
+ * Classical GA (reading of "roulette wheel selection ... single point
+ * crossover ... with randomly paired individuals ... mutation kept the same"):
+ * fitness F_i = max(E_max - obj_i, 0) (eq. (13)); slot i's parent is the
+ * first individual whose running fitness sum (index order) exceeds
+ * floor(hi32(w) * sum F / 2^32), w word 0 of slot i's purpose-6 block (a
+ * uniform individual, floor(hi32(w) * pop / 2^32), if every fitness is 0).
+ * The spins are independent, so consecutive slots (2k, 2k+1) are a random
+ * pairing of the selected parents: with p_c (slot 2k's purpose-1 block, as in
+ * the hybrid GA) they exchange tails at the same cut with correction, else
+ * they keep their parents; a last unpaired slot keeps its parent. Swap
+ * mutation as the hybrid GA. Replacement as the hybrid GA's with the whole
+ * population as one island (best-in-history kept, written over the worst).
+ *
+ * Cellular GA (reading of "two individuals are selected from a similar
+ * neighborhood area as the local asteroid selection ... single point
+ * crossover ... to generate a new individual ... same mutation ... replaces
+ * the target individual if its solution is better"): cell i's neighbourhood is
+ * itself and its four torus neighbours (order self, up, down, left, right);
+ * the two parents are its best two entries by (objective, order); with p_c
+ * (cell i's purpose-1 block) the child is the best's head and the second's
+ * tail at the cut, corrected, else a copy of the best; swap mutation as the
+ * hybrid GA; the child replaces cell i when its objective is strictly lower.
+ * The elite (best in history) is the lowest objective, lowest cell on ties. */
+#define ORC_GA_CLASSICAL 1
+#define ORC_GA_CELLULAR 2
+int64_t orc_emax(const int64_t *obj, int32_t pop);
+int orc_ga_generation_scheme(const orc_instance *in, const orc_ga_params *gp, int32_t scheme,
+                             int64_t e_max, uint64_t seed, uint64_t shop, int32_t event,
+                             int32_t gen, const int32_t *prio_in, const int64_t *obj_in,
+                             const int32_t *elite_in, const int64_t *elite_obj_in,
+                             int32_t *prio_out, int64_t *obj_out, int32_t *elite_out,
+                             int64_t *elite_obj_out, int32_t n_threads);
+
 /* Predictive-reactive rescheduling (Section 4.1, eq. (10)): freeze every op of
  * the executed plan that started before rs, append the n_new arrived jobs and
  * produce the next event's instance. */

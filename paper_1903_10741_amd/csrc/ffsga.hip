@@ -71,6 +71,7 @@ struct Header {
   unsigned long long work;  // algorithmic work of every decode of a GA
   int32_t span_max;     // longest schedule (end - RS) of a sizing decode (FFS_LDS_AUTO)
   int32_t n_fixed;      // planned ops kept in place (reschedule_static)
+  int64_t e_max;        // eq. (13)'s E_max of a classical GA (FFS_GA_CLASSICAL)
 };
 static_assert(sizeof(Header) <= kHeaderBytes, "header");
 
@@ -778,32 +779,23 @@ __device__ __forceinline__ int slot_of_block(int b, int K, int islands) {
 // with correction, swap mutation. Crossover and mutation draw from Philox
 // block `variant` (0 for the plain generation; the screened generation's
 // candidates use 0..V-1). Every lane calls this.
-__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l, int variant = 0,
-                            bool store = true) {
+// Build slot i's child in l.gene (and store it in A.prio_out unless !store) from
+// its parent `mine` and, when cross_idx >= 0, the partner parent `other`:
+// slot cross_idx's purpose-1 block decides the crossover (p_c) and its cut, the
+// child is mine's head and other's tail, corrected (Fig. 11); then slot i's
+// purpose-2 block decides the swap mutation (Fig. 12). Both Philox blocks are
+// evaluated together on two lanes (the scalar unit, which the CU's waves
+// share, is the busier one). Every lane calls this.
+__device__ void build_child(const GaDev &A, int n, int i, int gen, const Lds &l,
+                            const int32_t *mine, const int32_t *other, int cross_idx,
+                            int variant, bool store) {
   const int lane = __lane_id();
-  const int K = A.rows * A.cols;
   int32_t *first_pos = l.jobs;  // n + 1 words, then n words in rdy: free before the decode
   int32_t *miss = l.rdy;
-  // Pair (Fig. 10 is not available; reading: horizontal neighbours
-  // (r,2c)-(r,2c+1) on odd generations, vertical (2r,c)-(2r+1,c) on even).
-  const int loc = i % K, r = loc / A.cols, c = loc % A.cols;
-  int lead = -1, partner = -1;
-  if (gen & 1) {
-    if ((c | 1) < A.cols) {
-      lead = i - (c & 1);
-      partner = (c & 1) ? i - 1 : i + 1;
-    }
-  } else if ((r | 1) < A.rows) {
-    lead = i - (r & 1) * A.cols;
-    partner = (r & 1) ? i - A.cols : i + A.cols;
-  }
-  // The crossover block (lane 0: the pair leader's purpose 1) and the mutation
-  // block (other lanes: this slot's purpose 2) in one vector evaluation: the
-  // scalar unit, which the CU's waves share, is the busier one.
   u64 dw[4];
   {
     const bool xl = lane == 0;
-    philox((u64)(xl ? lead : i), (u64)gen, (u64)A.event,
+    philox((u64)(xl ? cross_idx : i), (u64)gen, (u64)A.event,
            ((xl ? 1ull : 2ull) << 32) | (u64)variant, A.seed, A.shop, dw);
   }
   const uint32_t xw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 0);
@@ -811,16 +803,13 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
   const uint32_t mw0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[0] >> 32), 1);
   const uint32_t mw1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[1] >> 32), 1);
   const uint32_t mw2 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(dw[2] >> 32), 1);
-  const int w_self = select_winner(A, i);
-  const int32_t *mine = A.prio_in + (size_t)w_self * n;
   bool cross = false;
   int cut = n;
-  if (lead >= 0 && n >= 2) {
+  if (cross_idx >= 0 && n >= 2) {
     cross = xw0 < A.pc;
     cut = 1 + (int)draw_below((u64)xw1 << 32, (uint32_t)(n - 1));
   }
   if (cross) {
-    const int32_t *other = A.prio_in + (size_t)select_winner(A, partner) * n;
     for (int k = lane; k < n; k += kWave) l.gene[k] = k < cut ? mine[k] : other[k];
     __asm__ volatile("" ::: "memory");
     correct_lds(l.gene, n, first_pos, miss);
@@ -844,6 +833,32 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
   if (!store) return;
   int32_t *dst = A.prio_out + (size_t)i * n;
   for (int k = lane; k < n; k += kWave) dst[k] = l.gene[k];
+}
+
+// Build the child of slot i for generation gen in l.gene (and store it in
+// A.prio_out): local selection of both parents, neighbour-paired crossover
+// with correction, swap mutation. Crossover and mutation draw from Philox
+// block `variant` (0 for the plain generation; the screened generation's
+// candidates use 0..V-1). Every lane calls this.
+__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l, int variant = 0,
+                            bool store = true) {
+  const int K = A.rows * A.cols;
+  // Pair (Fig. 10 is not available; reading: horizontal neighbours
+  // (r,2c)-(r,2c+1) on odd generations, vertical (2r,c)-(2r+1,c) on even).
+  const int loc = i % K, r = loc / A.cols, c = loc % A.cols;
+  int lead = -1, partner = -1;
+  if (gen & 1) {
+    if ((c | 1) < A.cols) {
+      lead = i - (c & 1);
+      partner = (c & 1) ? i - 1 : i + 1;
+    }
+  } else if ((r | 1) < A.rows) {
+    lead = i - (r & 1) * A.cols;
+    partner = (r & 1) ? i - A.cols : i + A.cols;
+  }
+  const int32_t *mine = A.prio_in + (size_t)select_winner(A, i) * n;
+  const int32_t *other = lead >= 0 ? A.prio_in + (size_t)select_winner(A, partner) * n : mine;
+  build_child(A, n, i, gen, l, mine, other, lead, variant, store);
 }
 
 // Generation 0 of slot i: Fisher-Yates over 1..n, draw d from word d % 4 of
@@ -946,6 +961,166 @@ __device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
   for (int k = lane; k < n; k += kWave)
     A.prio_out[(size_t)(base + w) * n + k] = A.elite[(size_t)I * n + k];
   if (lane == 0) A.obj_out[base + w] = bv < old ? bv : old;
+}
+
+
+// ---------------------------------------------------------------------------
+// The comparison GAs of Section 5.2 on job-priority vectors, one population of
+// rows x cols individuals (islands = 1): the classical GA (roulette wheel on
+// eq. (13)'s fitness, random pairing) and the cellular GA (parents from the
+// neighbourhood, replace if better).
+// ---------------------------------------------------------------------------
+// E_max of eq. (13): 10^a, the least a >= 1 above every objective of generation 0.
+__global__ __launch_bounds__(256) void emax_kernel(const int64_t *obj, int pop, Header *h) {
+  __shared__ int64_t sh[256];
+  const int t = threadIdx.x;
+  int64_t m = LLONG_MIN;
+  for (int i = t; i < pop; i += 256) m = max(m, obj[i]);
+  sh[t] = m;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sh[t] = max(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    int64_t e = 10;
+    while (!(sh[0] < e) && e <= LLONG_MAX / 10) e *= 10;
+    h->e_max = e;
+  }
+}
+
+// Running sums of eq. (13)'s fitness F_i = max(E_max - obj_i, 0) in index
+// order (integers: any order of additions gives the same sums). Thread t of
+// one block of 1024 sums a run of consecutive entries; the runs' totals are
+// scanned and each run then writes its running sums.
+__global__ __launch_bounds__(1024) void fitness_scan_kernel(const int64_t *obj, int pop,
+                                                            const Header *h, u64 *prefix) {
+  __shared__ u64 part[1024];
+  const int t = threadIdx.x;
+  const int64_t e = h->e_max;
+  const int c = (pop + 1023) / 1024;
+  const int a = min(t * c, pop), b = min(a + c, pop);
+  u64 sum = 0;
+  for (int i = a; i < b; ++i) {
+    const int64_t f = e - obj[i];
+    sum += f > 0 ? (u64)f : 0ull;
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const u64 v = t >= d ? part[t - d] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  u64 run = t > 0 ? part[t - 1] : 0ull;
+  for (int i = a; i < b; ++i) {
+    const int64_t f = e - obj[i];
+    run += f > 0 ? (u64)f : 0ull;
+    prefix[i] = run;
+  }
+}
+
+// Roulette spin of slot s (word 0 of its purpose-6 block): the first
+// individual whose running fitness sum exceeds floor(hi32 * total / 2^32), a
+// uniform one when every fitness is 0. The wave narrows the range 64-fold per
+// step, each lane testing the last running sum of one of 64 sub-ranges (the
+// first sub-range whose last sum exceeds the target holds the answer).
+__device__ int roulette_spin(const GaDev &A, const u64 *prefix, int pop, int s, int gen) {
+  u64 w[4];
+  philox((u64)s, (u64)gen, (u64)A.event, 6ull << 32, A.seed, A.shop, w);
+  const u64 total = prefix[pop - 1];
+  if (total == 0) return (int)draw_below(w[0], (uint32_t)pop);
+  const u64 target = __umul64hi((w[0] >> 32) << 32, total);
+  const int lane = __lane_id();
+  int lo = 0, hi = pop;  // the answer lies in [lo, hi) and prefix[hi - 1] > target
+  while (hi - lo > kWave) {
+    const int step = (hi - lo + kWave - 1) / kWave;
+    const int e = min(lo + (lane + 1) * step, hi) - 1;
+    const u64 m = ballot64(prefix[e] > target);
+    const int f = __ffsll((long long)m) - 1;
+    const int nlo = lo + f * step;
+    hi = min(nlo + step, hi);
+    lo = nlo;
+  }
+  const u64 m = ballot64(lo + lane < hi && prefix[min(lo + lane, hi - 1)] > target);
+  return lo + __ffsll((long long)m) - 1;
+}
+
+// Classical GA, one wave per slot: the slot's and its pair partner's parents by
+// roulette, the pair (2k, 2k+1) crossing at slot 2k's cut, swap mutation, decode.
+template <int MAXM>
+__global__ __launch_bounds__(64) void classical_generation_kernel(DInst I, GaDev A, int gen,
+                                                                  int cap, const u64 *prefix) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int i = blockIdx.x, pop = A.rows * A.cols, partner = i ^ 1;
+  const Lds l = carve_lds(smem, I.n);
+  const int32_t *mine = A.prio_in + (size_t)roulette_spin(A, prefix, pop, i, gen) * I.n;
+  if (partner < pop) {
+    const int32_t *other = A.prio_in + (size_t)roulette_spin(A, prefix, pop, partner, gen) * I.n;
+    build_child(A, I.n, i, gen, l, mine, other, i & ~1, 0, true);
+  } else {
+    build_child(A, I.n, i, gen, l, mine, mine, -1, 0, true);
+  }
+  decode_and_record<MAXM>(I, A, i, cap, l, i);
+}
+
+// Cellular GA, one wave per cell: the best two of the cell and its four torus
+// neighbours (by objective, then in the order self, up, down, left, right),
+// crossing at the cell's own cut, swap mutation, decode.
+template <int MAXM>
+__global__ __launch_bounds__(64) void cellular_generation_kernel(DInst I, GaDev A, int gen,
+                                                                 int cap) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int i = blockIdx.x, R = A.rows, C = A.cols, r = i / C, c = i % C;
+  const Lds l = carve_lds(smem, I.n);
+  const int cand[5] = {i, ((r + R - 1) % R) * C + c, ((r + 1) % R) * C + c,
+                       r * C + (c + C - 1) % C, r * C + (c + 1) % C};
+  int64_t o[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) o[k] = ld_const(A.obj_in, (size_t)cand[k]);
+  int b1 = 0, b2 = -1;
+#pragma unroll
+  for (int k = 1; k < 5; ++k)
+    if (o[k] < o[b1]) b1 = k;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (k != b1 && (b2 < 0 || o[k] < o[b2])) b2 = k;
+  build_child(A, I.n, i, gen, l, A.prio_in + (size_t)cand[b1] * I.n,
+              A.prio_in + (size_t)cand[b2] * I.n, i, 0, true);
+  decode_and_record<MAXM>(I, A, i, cap, l, i);
+}
+
+// Cellular replacement: a cell keeps its previous individual unless the child
+// is strictly better (one wave per cell, after any off-chip redo).
+__global__ __launch_bounds__(64) void cellular_accept_kernel(const int32_t *prio_in,
+                                                             const int64_t *obj_in,
+                                                             int32_t *prio_out, int64_t *obj_out,
+                                                             int n) {
+  const int i = blockIdx.x;
+  if (obj_out[i] < obj_in[i]) return;
+  for (int k = __lane_id(); k < n; k += kWave) prio_out[(size_t)i * n + k] = prio_in[(size_t)i * n + k];
+  if (__lane_id() == 0) obj_out[i] = obj_in[i];
+}
+
+// Best in history of a whole population (lowest objective, lowest slot on ties).
+__global__ __launch_bounds__(64) void elite_update_kernel(const int32_t *prio, const int64_t *obj,
+                                                          int32_t *elite, int64_t *elite_obj,
+                                                          int pop, int n) {
+  int64_t bv = LLONG_MAX;
+  int b = INT_MAX;
+  for (int k = __lane_id(); k < pop; k += kWave) {
+    const int64_t o = obj[k];
+    if (o < bv) {
+      bv = o;
+      b = k;
+    }
+  }
+  wave_arg<false>(bv, b);
+  if (bv < elite_obj[0]) {
+    for (int k = __lane_id(); k < n; k += kWave) elite[k] = prio[(size_t)b * n + k];
+    if (__lane_id() == 0) elite_obj[0] = bv;
+  }
 }
 
 template <int MAXM>
@@ -2453,6 +2628,7 @@ struct GaLayout {
   int64_t *stage_obj;
   int32_t *ovf_list;
   int32_t *xyop, *xyg0;  // X/Y gene table (encoding 1)
+  u64 *prefix;           // running fitness sums (FFS_GA_CLASSICAL)
   uint8_t *gprof;
   size_t gstride, total;
   bool inline_redo;  // one off-chip profile per individual: no overflow kernel
@@ -2493,6 +2669,10 @@ GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int
   off += align_up((size_t)p->islands * kk * 8, 256);
   L.ovf_list = (int32_t *)(b + off);
   off += align_up(pop * 4, 256);
+  if (p->scheme == FFS_GA_CLASSICAL) {
+    L.prefix = (u64 *)(b + off);
+    off += align_up(pop * 8, 256);
+  }
   if (p->encoding == 1) {
     L.xyop = (int32_t *)(b + off);
     off += align_up((size_t)4 * in->n_ops + 4, 256);
@@ -2535,6 +2715,9 @@ int check_ga_params(const ffs_ga_params *p) {
   if (p->mig_k > K) return FFS_E_INVAL;
   if (K > 65536 || K * p->islands > (1 << 26)) return FFS_E_UNSUPPORTED;
   if (p->encoding != 0 && p->encoding != 1) return FFS_E_INVAL;
+  if (p->scheme != FFS_GA_HYBRID && p->scheme != FFS_GA_CLASSICAL && p->scheme != FFS_GA_CELLULAR)
+    return FFS_E_INVAL;
+  if (p->scheme != FFS_GA_HYBRID && (p->islands != 1 || p->encoding != 0)) return FFS_E_INVAL;
   return FFS_OK;
 }
 
@@ -2617,6 +2800,10 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
              (const int32_t *)L.prio[0], (const int64_t *)L.obj[0], L.elite, L.elite_obj, K,
              n) != hipSuccess)
     return FFS_E_DEVICE;
+  if (ga->params.scheme == FFS_GA_CLASSICAL &&
+      launch(-1, emax_kernel, dim3(1), dim3(256), 0, stream, (const int64_t *)L.obj[0], pop,
+             L.hdr) != hipSuccess)
+    return FFS_E_DEVICE;
   if (auto_cap) {
     // later generations keep 5/4 of generation 0's longest schedule + 64 slots on chip
     Header host;
@@ -2652,7 +2839,17 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     const int cur = ga->cur;
     GaDev A = make_gadev(ga, L, cur);
     hipError_t e;
-    if (scr)
+    const int32_t scheme = ga->params.scheme;
+    if (scheme == FFS_GA_CLASSICAL) {
+      if (launch(-1, fitness_scan_kernel, dim3(1), dim3(1024), 0, stream,
+                 (const int64_t *)A.obj_in, pop, (const Header *)L.hdr, L.prefix) != hipSuccess)
+        return FFS_E_DEVICE;
+      e = launch(1, classical_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A,
+                 gen, cap, (const u64 *)L.prefix);
+    } else if (scheme == FFS_GA_CELLULAR) {
+      e = launch(1, cellular_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A,
+                 gen, cap);
+    } else if (scr)
       e = launch(5, ga_screened_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen, cap,
                  scr->table, scr->theta, scr->variants, scr->scores, scr->choice);
     else if (xy)
@@ -2664,6 +2861,18 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     if (e != hipSuccess) return FFS_E_DEVICE;
     int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream, xy);
     if (rc) return rc;
+    if (scheme == FFS_GA_CELLULAR) {
+      if (launch(2, cellular_accept_kernel, dim3(pop), dim3(kWave), 0, stream,
+                 (const int32_t *)L.prio[cur], (const int64_t *)L.obj[cur], L.prio[1 - cur],
+                 L.obj[1 - cur], n) != hipSuccess ||
+          launch(2, elite_update_kernel, dim3(1), dim3(kWave), 0, stream,
+                 (const int32_t *)L.prio[1 - cur], (const int64_t *)L.obj[1 - cur], L.elite,
+                 L.elite_obj, pop, n) != hipSuccess)
+        return FFS_E_DEVICE;
+      ga->cur = 1 - cur;
+      ga->generation = gen;
+      continue;
+    }
     if (launch(2, replace_wave_kernel, dim3(ga->params.islands), dim3(kWave), 0, stream,
                L.prio[1 - cur], L.obj[1 - cur], L.elite, L.elite_obj, K, n) != hipSuccess)
       return FFS_E_DEVICE;
@@ -2700,6 +2909,10 @@ void set_lds_limits() {
   (void)hipFuncSetAttribute((const void *)ga_init_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void *)ga_screened_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)classical_generation_kernel<MAXM>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  (void)hipFuncSetAttribute((const void *)cellular_generation_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   (void)hipFuncSetAttribute((const void *)decode_xy_kernel<MAXM>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -2783,7 +2996,8 @@ int check_batch_params(const ffs_batch_params *p) {
     return FFS_E_INVAL;
   int rc = check_ga_params(&p->ga);
   if (rc) return rc;
-  if (p->ga.encoding != 0) return FFS_E_UNSUPPORTED;  // batches run job-priority chromosomes
+  if (p->ga.encoding != 0 || p->ga.scheme != FFS_GA_HYBRID)
+    return FFS_E_UNSUPPORTED;  // batches run the hybrid GA on job-priority chromosomes
   if (p->n_slots > FFS_BATCH_MAX_SLOTS || p->o_max > 16 || p->max_genes > kMaxGenes ||
       p->max_stages > kMaxStages || p->max_jobs >= (1 << 20) || p->max_horizon >= kMaxTime)
     return FFS_E_UNSUPPORTED;
@@ -3221,7 +3435,8 @@ int ga_step_screened(ffs_ga *ga, const ffs_instance *inst, const ffs_surrogate *
                      int32_t *choice, void *stream) {
   int rc = check_host(inst);
   if (rc) return rc;
-  if (ga && ga->params.encoding != 0) return FFS_E_UNSUPPORTED;
+  if (ga && (ga->params.encoding != 0 || ga->params.scheme != FFS_GA_HYBRID))
+    return FFS_E_UNSUPPORTED;
   if (!ga || !ga->workspace || n_generations < 0 || inst->n_active != ga->n_genes ||
       inst->n_jobs != ga->n_jobs || inst->horizon != ga->horizon || !model || !model->theta ||
       !table || variants < 1 || variants > FFS_SG_MAX_VARIANTS ||
@@ -3247,6 +3462,7 @@ int ga_view(const ffs_ga *ga, ffs_ga_view *view) {
   view->elite = ga->elite;
   view->elite_obj = ga->elite_obj;
   view->work = (int64_t *)&((Header *)ga->workspace)->work;
+  view->e_max = &((Header *)ga->workspace)->e_max;
   return FFS_OK;
 }
 

@@ -26,6 +26,7 @@ FFS_E_UNSUPPORTED = -5
 FFS_PREPARE_WORKSPACE = 256
 FFS_DECODE_SCRATCH_BYTES = 16 << 20
 FFS_LDS_AUTO = -1
+FFS_GA_HYBRID, FFS_GA_CLASSICAL, FFS_GA_CELLULAR = 0, 1, 2
 
 TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
 TIMING_BATCH, TIMING_SCREENED = 4, 5
@@ -60,7 +61,7 @@ class FfsGaParams(ctypes.Structure):
         ("islands", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
         ("pc", ctypes.c_uint32), ("pm", ctypes.c_uint32),
         ("mig_interval", ctypes.c_int32), ("mig_k", ctypes.c_int32),
-        ("lds_slots", ctypes.c_int32), ("encoding", ctypes.c_int32),
+        ("lds_slots", ctypes.c_int32), ("encoding", ctypes.c_int32), ("scheme", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,8 @@ class FfsGa(ctypes.Structure):
 
 
 class FfsGaView(ctypes.Structure):
-    _fields_ = [("prio", _vp), ("obj", _vp), ("elite", _vp), ("elite_obj", _vp), ("work", _vp)]
+    _fields_ = [("prio", _vp), ("obj", _vp), ("elite", _vp), ("elite_obj", _vp), ("work", _vp),
+                ("e_max", _vp)]
 
 
 _P = ctypes.POINTER
@@ -297,16 +299,17 @@ class GaConfig:
     mig_k: int = 1
     lds_slots: int = 0
     encoding: int = 0   # 0: one priority per job; 1: X/Y matrices (2 * n_ops genes)
+    scheme: int = 0     # FFS_GA_HYBRID, FFS_GA_CLASSICAL or FFS_GA_CELLULAR
 
     @classmethod
-    def of(cls, ga, lds_slots=0, encoding=None):
+    def of(cls, ga, lds_slots=0, encoding=None, scheme=0):
         enc = getattr(ga, "encoding", 0) if encoding is None else encoding
         return cls(ga.islands, ga.rows, ga.cols, ga.pc, ga.pm, ga.mig_interval, ga.mig_k, lds_slots,
-                   enc)
+                   enc, scheme)
 
     def c(self):
         return FfsGaParams(self.islands, self.rows, self.cols, self.pc, self.pm, self.mig_interval,
-                           self.mig_k, self.lds_slots, self.encoding)
+                           self.mig_k, self.lds_slots, self.encoding, self.scheme)
 
 
 class GA:
@@ -374,6 +377,12 @@ class GA:
             "elite_obj": self._slice(v.elite_obj, isl, torch.int64),
             "work": self._slice(v.work, 1, torch.int64),
         }
+
+    def e_max(self):
+        """E_max of eq. (13) set by ga_init for FFS_GA_CLASSICAL (0 otherwise)."""
+        v = FfsGaView()
+        _check(_lib.ga_view(ctypes.byref(self.ga), ctypes.byref(v)), "ga_view")
+        return int(self._slice(v.e_max, 1, torch.int64).item())
 
 
 def reschedule(prev: DeviceInstance, plan_start: torch.Tensor, plan_mach: torch.Tensor, arrival,

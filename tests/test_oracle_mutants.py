@@ -19,7 +19,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "ffs_oracle.c")
 PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_init_work.py", "tests/test_oracle_xy.py",
-        "tests/test_oracle_rules.py", "tests/test_oracle_static.py"]
+        "tests/test_oracle_rules.py", "tests/test_oracle_static.py",
+        "tests/test_oracle_schemes.py"]
 
 # (name, text in ffs_oracle.c (must occur once), replacement)
 MUTANTS = [
@@ -70,6 +71,18 @@ MUTANTS = [
      "      d->profile[tau] += q;\n  }\n  return ORC_OK;", "      ;\n  }\n  return ORC_OK;"),
     ("static: op running at RS dropped", "if (st < rs && end > rs) {  /* running at RS",
      "if (0) {  /* running at RS"),
+    # the comparison GAs of Section 5.2
+    ("E_max one power of ten short", "if (below || e > INT64_MAX / 10) return e;",
+     "if (below || e > INT64_MAX / 10) return e / 10 > 1 ? e / 10 : e;"),
+    ("roulette picks the first sum at or above the target", "if (prefix[i] > hi) return i;",
+     "if (prefix[i] >= hi) return i;"),
+    ("roulette fitness without the zero floor", "total += f > 0 ? (uint64_t)f : 0;",
+     "total += (uint64_t)f;"),
+    ("cellular second parent is the worst", "if (k != b1 && (b2 < 0 || obj_in[cand[k]] < obj_in[cand[b2]])) b2 = k;",
+     "if (k != b1 && (b2 < 0 || obj_in[cand[k]] > obj_in[cand[b2]])) b2 = k;"),
+    ("cellular replaces on ties", "const int better = cobj[i] < obj_in[i];",
+     "const int better = cobj[i] <= obj_in[i];"),
+    ("cellular always replaces", "const int better = cobj[i] < obj_in[i];", "const int better = 1;"),
     # random numbers and initialisation
     ("Philox key schedule", "k0 += W0;", "k0 += W1;"),
     ("Sattolo shuffle", "int32_t r = (int32_t)draw_below(w[d % 4], (uint32_t)(pos + 1));",
