@@ -241,7 +241,8 @@ def bench_large(args):
         decodes += ev.decodes
         events.append(ev)
         per_event.append({"event": ev.event, "n_active": ev.n_active, "lds_slots": ev.lds_slots,
-                          "s": dt, "decodes_per_s": ev.decodes / dt})
+                          "s": dt, "decodes_per_s": ev.decodes / dt,
+                          "decodes_redone_off_chip": ev.overflows})
         progress(f"large step {k + 1}: event {ev.event}, {ev.n_active} jobs, "
                  f"{ev.lds_slots} on-chip slots, {dt:.2f} s")
     torch.cuda.synchronize()
@@ -430,52 +431,57 @@ def bench_rs_ratio(args):
 def bench_schemes(args):
     """Section 5.2, Tables 8-9: the hybrid GA (8x8 islands, ring migration) against
     the classical GA (roulette wheel on eq. (13), random pairing) and the cellular
-    GA (neighbourhood parents, replace if better), all on the GPU, on Table
-    5-shaped instances (10 jobs, 3 stages of 2 machines, power peak 4, WT = 100)
-    at populations 64x64, 128x128 and 256x256, 100 generations from the same
-    seed: best objective (mean and best over the instances) and wall time per
-    100 generations (init included)."""
+    GA (neighbourhood parents, replace if better), all on the GPU, at populations
+    64x64, 128x128 and 256x256, 100 generations from the same seed, on two
+    instance families: Table 5-shaped (10 jobs, 3 stages of 2 machines, power peak
+    4, WT = 100: the paper's test 2 size) and paper-50x5x3 event 0 (50 jobs).
+    Per scheme: best objective (mean and best over the instances) and wall time
+    per 100 generations (init included)."""
     import numpy as np
     import torch
     from paper_1903_10741_amd import ffsga
     from paper_1903_10741_amd import workloads as W
     gens = args.generations or 100
     paper_s = {64: (8.77, 8.14, 129.16), 128: (30.71, 31.13, 554.01), 256: (105.73, 108.07, 2651.61)}
+    families = (("table5-10x3x2", W.table5_instance), ("paper-50x5x3", lambda sd: W.config2(sd).initial))
     rows = []
-    for side in (64, 128, 256):
-        per = {}
-        for name, scheme, gp in (("hybrid", ffsga.FFS_GA_HYBRID, W.GaParams(side * side // 64, 8, 8)),
-                                 ("classical", ffsga.FFS_GA_CLASSICAL, W.GaParams(1, side, side)),
-                                 ("cellular", ffsga.FFS_GA_CELLULAR, W.GaParams(1, side, side))):
-            cfg = ffsga.GaConfig.of(gp, scheme=scheme)
-            objs, times = [], []
-            for sd in range(args.seed, args.seed + args.instances):
-                d = ffsga.DeviceInstance.from_host(W.table5_instance(sd))
-                if sd == args.seed:   # warm-up of this launch shape
-                    ffsga.GA(d, cfg, sd, 0, 0).step(2)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                g = ffsga.GA(d, cfg, sd, 0, 0)
-                g.step(gens)
-                best = int(g.best()[1].item())
-                times.append(time.perf_counter() - t0)
-                objs.append(best)
-            per[name] = {"mean_best_obj": float(np.mean(objs)), "best_obj": int(min(objs)),
-                         "s_per_100_generations": float(np.mean(times)) * 100 / gens,
-                         "decodes_per_s": (1 + gens) * gp.pop / float(np.mean(times))}
-            progress(f"{side}x{side} {name}: mean best {np.mean(objs):.1f}, "
-                     f"{np.mean(times) * 1e3:.1f} ms per run")
-        rows.append({"population": f"{side}x{side}", **per,
-                     "paper_k40_s_per_100_generations": {"hybrid": paper_s[side][0],
-                                                         "cellular": paper_s[side][1],
-                                                         "classical_1_cpu_core": paper_s[side][2]}})
+    for fam, make in families:
+        for side in (64, 128, 256):
+            per = {}
+            for name, scheme, gp in (("hybrid", ffsga.FFS_GA_HYBRID,
+                                      W.GaParams(side * side // 64, 8, 8)),
+                                     ("classical", ffsga.FFS_GA_CLASSICAL, W.GaParams(1, side, side)),
+                                     ("cellular", ffsga.FFS_GA_CELLULAR, W.GaParams(1, side, side))):
+                cfg = ffsga.GaConfig.of(gp, scheme=scheme)
+                objs, times = [], []
+                for sd in range(args.seed, args.seed + args.instances):
+                    d = ffsga.DeviceInstance.from_host(make(sd))
+                    if sd == args.seed:   # warm-up of this launch shape
+                        ffsga.GA(d, cfg, sd, 0, 0).step(2)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g = ffsga.GA(d, cfg, sd, 0, 0)
+                    g.step(gens)
+                    best = int(g.best()[1].item())
+                    times.append(time.perf_counter() - t0)
+                    objs.append(best)
+                per[name] = {"mean_best_obj": float(np.mean(objs)), "best_obj": int(min(objs)),
+                             "s_per_100_generations": float(np.mean(times)) * 100 / gens,
+                             "decodes_per_s": (1 + gens) * gp.pop / float(np.mean(times))}
+                progress(f"{fam} {side}x{side} {name}: mean best {np.mean(objs):.1f}, "
+                         f"{np.mean(times) * 1e3:.1f} ms per run")
+            rows.append({"instances": fam, "population": f"{side}x{side}", **per,
+                         "paper_k40_s_per_100_generations": {
+                             "hybrid": paper_s[side][0], "cellular": paper_s[side][1],
+                             "classical_1_cpu_core": paper_s[side][2],
+                             "note": "the paper's own small instances (10 jobs, 3 stages x 2 "
+                                     "machines), K40 and Xeon E5640"}})
     out = common(args, "wall time per 100 generations, hybrid vs classical vs cellular GA",
-                 rows[0]["hybrid"]["s_per_100_generations"], "s (hybrid GA, 64x64)",
+                 rows[0]["hybrid"]["s_per_100_generations"], "s (hybrid GA, 64x64, Table 5-shaped)",
                  sum(r[k]["s_per_100_generations"] for r in rows
                      for k in ("hybrid", "classical", "cellular")) * 1e3, "int32", {
-                     "workload": f"Table 5-shaped instances {args.seed}-"
-                                 f"{args.seed + args.instances - 1} (10 jobs, 3 stages x 2 machines, "
-                                 f"Q_max 4, WT 100), {gens} generations per run",
+                     "workload": f"instances {args.seed}-{args.seed + args.instances - 1} of each "
+                                 f"family, {gens} generations per run, job-priority vectors",
                      "table": rows})
     out["higher_is_better"] = False
     out["steps"] = 1

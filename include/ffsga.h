@@ -253,6 +253,8 @@ typedef struct {
   int64_t *work;       /* [1]: algorithmic work summed over every decode since ga_init
                           (same count as ffs_decode's work output) */
   int64_t *e_max;      /* [1]: E_max of eq. (13) (FFS_GA_CLASSICAL; 0 otherwise) */
+  int64_t *overflows;  /* [1]: job-vector decodes since ga_init whose schedule outgrew the
+                          on-chip profile and were redone off chip (same results) */
 } ffs_ga_view;
 
 size_t ffs_ga_workspace_size(const ffs_instance *inst, const ffs_ga_params *params);

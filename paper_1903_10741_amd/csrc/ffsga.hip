@@ -72,6 +72,7 @@ struct Header {
   int32_t span_max;     // longest schedule (end - RS) of a sizing decode (FFS_LDS_AUTO)
   int32_t n_fixed;      // planned ops kept in place (reschedule_static)
   int64_t e_max;        // eq. (13)'s E_max of a classical GA (FFS_GA_CLASSICAL)
+  unsigned long long overflows;  // decodes of a GA that outgrew the on-chip profile
 };
 static_assert(sizeof(Header) <= kHeaderBytes, "header");
 
@@ -277,16 +278,16 @@ __device__ __forceinline__ void GlobalProfile::commit(int t, int p, int q) const
 enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 
 // LDS of one wave (one chromosome of n genes; words of a packed P|Q row per op):
-//   gene  [n]        the chromosome (input)
-//   jobs  [n]        by rank: job | first_stage << 24  (correction scratch before decode)
-//   rdy   [n]        by rank: completion of the job's last placed stage
+//   jobs  [n+1]      by rank: job | first_stage << 24  (correction scratch before decode)
+//   rdy   [n+1]      by rank: completion of the job's last placed stage (scratch before)
 //   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20);
 //                    a placed op's earliest start is overwritten by its end time
+//   gene  [n]        the chromosome (input), in the first half of op's region: it is
+//                    dead once the decode has built the ranks, before any op record
 //   rec   [2][kRing] packed P | Q << 16 rows of the stage's ops, one word per machine,
 //                    staged from the packed table kWave / o_s ops at a time, double buffered
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
-// gene is free once the ranks are built.
 struct Lds {
   int32_t *gene, *jobs, *rdy;
   int2 *op;
@@ -299,18 +300,18 @@ struct Lds {
 constexpr int kRing = kWave + 16;
 
 __host__ __device__ inline size_t lds_bytes(int n, int cap) {
-  return 3 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) + 8 * kRing +
+  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) + 8 * kRing +
          (cap > 0 ? align_up(cap, 16) + kWave : 0);
 }
 
 __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   Lds l;
   const size_t a = align_up((size_t)4 * n + 4, 16);
-  l.gene = (int32_t *)smem;
-  l.jobs = (int32_t *)(smem + a);
-  l.rdy = (int32_t *)(smem + 2 * a);
-  l.op = (int2 *)(smem + 3 * a);
-  l.rec = (uint32_t *)(smem + 3 * a + align_up((size_t)8 * n + 8, 16));
+  l.jobs = (int32_t *)smem;
+  l.rdy = (int32_t *)(smem + a);
+  l.op = (int2 *)(smem + 2 * a);
+  l.gene = (int32_t *)l.op;
+  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)8 * n + 8, 16));
   l.prof = (uint8_t *)l.rec + 8 * kRing;
   return l;
 }
@@ -865,7 +866,7 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
 // block d / 4 of purpose 0; the result goes to l.gene and A.prio_out.
 __device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
   const int lane = __lane_id();
-  uint32_t *hi = (uint32_t *)l.op;  // n - 1 high words
+  uint32_t *hi = (uint32_t *)l.rdy;  // n - 1 high words (rdy is scratch before the decode)
   for (int k = lane; k < n; k += kWave) l.gene[k] = k + 1;
   const int n_blocks = (n - 1 + 3) / 4;
   for (int b = lane; b < n_blocks; b += kWave) {
@@ -899,7 +900,10 @@ __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap
   int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
                                     nullptr, span);
   // a schedule longer than the on-chip slots: at least cap + 1 of them
-  if (st == kDecOverflow && span && __lane_id() == 0) atomicMax(span, cap + 1);
+  if (st == kDecOverflow && __lane_id() == 0) {
+    atomicAdd(&A.hdr->overflows, 1ull);
+    if (span) atomicMax(span, cap + 1);
+  }
   if (st == kDecOverflow && A.redo_prof) {
     const int32_t *src = A.prio_out + (size_t)i * I.n;
     for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];  // this lane's own stores
@@ -3463,6 +3467,7 @@ int ga_view(const ffs_ga *ga, ffs_ga_view *view) {
   view->elite_obj = ga->elite_obj;
   view->work = (int64_t *)&((Header *)ga->workspace)->work;
   view->e_max = &((Header *)ga->workspace)->e_max;
+  view->overflows = (int64_t *)&((Header *)ga->workspace)->overflows;
   return FFS_OK;
 }
 

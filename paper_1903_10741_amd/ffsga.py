@@ -79,7 +79,7 @@ class FfsGa(ctypes.Structure):
 
 class FfsGaView(ctypes.Structure):
     _fields_ = [("prio", _vp), ("obj", _vp), ("elite", _vp), ("elite_obj", _vp), ("work", _vp),
-                ("e_max", _vp)]
+                ("e_max", _vp), ("overflows", _vp)]
 
 
 _P = ctypes.POINTER
@@ -377,6 +377,12 @@ class GA:
             "elite_obj": self._slice(v.elite_obj, isl, torch.int64),
             "work": self._slice(v.work, 1, torch.int64),
         }
+
+    def overflows(self):
+        """Decodes since ga_init redone off chip (their schedule outgrew the on-chip slots)."""
+        v = FfsGaView()
+        _check(_lib.ga_view(ctypes.byref(self.ga), ctypes.byref(v)), "ga_view")
+        return int(self._slice(v.overflows, 1, torch.int64).item())
 
     def e_max(self):
         """E_max of eq. (13) set by ga_init for FFS_GA_CLASSICAL (0 otherwise)."""
