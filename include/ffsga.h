@@ -218,11 +218,13 @@ typedef struct {
 /* ffs_ga_params.lds_slots = FFS_LDS_AUTO (job-priority vectors only; encoding 1
  * gets FFS_E_UNSUPPORTED): ga_init decodes generation 0 with as many on-chip
  * slots as one workgroup's LDS holds (at most 32768, no more than the horizon
- * needs), records the longest schedule (end - RS) and keeps 5/4 of it plus 64
- * slots (a multiple of 64) on chip for every later generation, so long
- * schedules stay on chip and short ones leave LDS for more waves per compute
- * unit. ga_init then synchronises its stream once and ffs_ga.lds_slots holds
- * the chosen slots. A later decode that outgrows them is redone off chip as
+ * needs) and records the longest schedule (end - RS). Every later generation
+ * keeps that schedule plus 1/16 of it and 64 slots on chip, widened to the
+ * most slots (a multiple of 64, at most the sizing decode's) at which a compute
+ * unit still holds as many waves of the generation kernel (the runtime's
+ * occupancy figure), so long schedules stay on chip and short ones leave LDS for
+ * more waves. ga_init then synchronises its stream once and ffs_ga.lds_slots
+ * holds the chosen slots. A later decode that outgrows them is redone off chip as
  * usual: results never depend on the choice. */
 #define FFS_LDS_AUTO (-1)
 

@@ -279,18 +279,18 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 
 // LDS of one wave (one chromosome of n genes; words of a packed P|Q row per op):
 //   jobs  [n+1]      by rank: job | first_stage << 24  (correction scratch before decode)
-//   rdy   [n+1]      by rank: completion of the job's last placed stage (scratch before)
-//   op    [n+1]      the current stage's ops in order: (earliest start, job | rank << 20);
-//                    a placed op's earliest start is overwritten by its end time
-//   gene  [n]        the chromosome (input), in the first half of op's region: it is
-//                    dead once the decode has built the ranks, before any op record
+//   rdy   [n+1]      by rank: completion of the job's last placed stage (scratch before);
+//                    an op's end replaces it as soon as the op is placed
+//   op    [n+2]      the current stage's ops in order, as ranks (two spare records that
+//                    the op loop prefetches past the last)
+//   gene  [n]        the chromosome (input), in op's region: it is dead once the decode
+//                    has built the ranks, before any op record
 //   rec   [2][kRing] packed P | Q << 16 rows of the stage's ops, one word per machine,
 //                    staged from the packed table kWave / o_s ops at a time, double buffered
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
 struct Lds {
-  int32_t *gene, *jobs, *rdy;
-  int2 *op;
+  int32_t *gene, *jobs, *rdy, *op;
   uint32_t *rec;
   uint8_t *prof;
 };
@@ -300,7 +300,7 @@ struct Lds {
 constexpr int kRing = kWave + 16;
 
 __host__ __device__ inline size_t lds_bytes(int n, int cap) {
-  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)8 * n + 8, 16) + 8 * kRing +
+  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)4 * n + 8, 16) + 8 * kRing +
          (cap > 0 ? align_up(cap, 16) + kWave : 0);
 }
 
@@ -309,9 +309,9 @@ __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   const size_t a = align_up((size_t)4 * n + 4, 16);
   l.jobs = (int32_t *)smem;
   l.rdy = (int32_t *)(smem + a);
-  l.op = (int2 *)(smem + 2 * a);
-  l.gene = (int32_t *)l.op;
-  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)8 * n + 8, 16));
+  l.op = (int32_t *)(smem + 2 * a);
+  l.gene = l.op;
+  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)4 * n + 8, 16));
   l.prof = (uint8_t *)l.rec + 8 * kRing;
   return l;
 }
@@ -447,12 +447,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
             k += (l.jobs[y] >> 24) <= s && (cy < cx || (cy == cx && y < x));
           }
         }
-        const int j = jf & 0xFFFFFF;
-        l.op[k] = make_int2(max(rs, l.rdy[x]), (int)((uint32_t)j | ((uint32_t)x << 20)));
+        l.op[k] = x;
       }
       cnt += __popcll(mk);
     }
-    if (lane == 0) l.op[cnt] = make_int2(0, 0);
+    if (lane < 2) l.op[cnt + lane] = 0;
     __asm__ volatile("" ::: "memory");
     // The ops' packed P|Q rows come from the packed table chunk by chunk: lane
     // lk * o_s + lm holds machine lm of op lk of a chunk of kWave / o_s ops.
@@ -464,7 +463,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     const size_t pq_job = (size_t)I.g * I.omp;
     auto row_word = [&](int k) -> uint32_t {
       if (lk >= C || k >= cnt) return 0u;
-      const int j = l.op[k].y & 0xFFFFF;
+      const int j = l.jobs[l.op[k]] & 0xFFFFFF;
       return pq_stage[(size_t)j * pq_job];
     };
     {
@@ -473,12 +472,17 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     }
     __asm__ volatile("" ::: "memory");
     // The record pointer as a per-lane value (the asm hides that the zero is
-    // uniform): records are then read and written through one vector address
-    // with immediate offsets instead of a scalar address moved in every op.
+    // uniform): records are then read through one vector address with immediate
+    // offsets instead of a scalar address moved in every op. The op loop reads
+    // the rank of the op after next and the ready time of the next op's job
+    // (the completion of its previous stage, still in rdy: each job has one op
+    // per stage) one op ahead, and writes each op's end into rdy at once.
     int vz;
     __asm__("v_mov_b32 %0, 0" : "=v"(vz));
-    int2 *opp = l.op + vz;
-    int2 o = *opp;
+    const int32_t *opp = l.op + vz;
+    int32_t *rdy_at = l.rdy + opp[0];  // the current op's job
+    int rk1 = opp[1];                  // the next op's rank
+    int ex = *rdy_at;                  // the current op's job's ready time
     // The stage's work sum, per lane (summed on the vector unit). Default rules:
     // the push-right intervals [t0, t) of one machine's ops are disjoint and lie
     // within the span after RS (< 2^27 slots), so over at most 16 machines they
@@ -497,10 +501,12 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     for (int k = base; k < k_end; ++k) {
       opp += 1;
       recp += os;
-      const int2 o_next = *opp;
+      const int rk2 = opp[1];
+      int32_t *const rdy_next = l.rdy + rk1;
+      const int ex_next = *rdy_next;
       const uint32_t pq_next = *recp;
       // Machine of earliest completion (ties to the lowest index).
-      const int mx = max(o.x, fr);
+      const int mx = max(max(ex, rs), fr);
       const int t0v = mx - rs;  // earliest start on this lane's machine, slots after RS
       const uint32_t key = ((uint32_t)(mx + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
       uint32_t kmin =
@@ -514,7 +520,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // machine of least key goes first, then in index order only machines whose
         // key is below the best so far. Work: 3 per machine, plus the examined
         // slots and p of every machine pushed right.
-        const int ox = uni(o.x);  // uniform: keeps this loop on the scalar unit
+        const int ox = uni(max(ex, rs));  // uniform: keeps this loop on the scalar unit
         const int first = (int)(kmin & 15u);
         uint32_t best = 0xFFFFFFFFu;
         cw = 3 * os;
@@ -550,9 +556,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       prof.commit(t, p, q);
       const int end = t + p + rs;
       fr = ffs_writelane(end, mb, fr);
-      opp[-1].x = PLAN ? end | (mb << 27) : end;
+      *rdy_at = PLAN ? end | (mb << 27) : end;
       stage_work = stage_work + cw;
-      o = o_next;
+      rdy_at = rdy_next;
+      rk1 = rk2;
+      ex = ex_next;
       pqv = pq_next;
     }
       if (lk < C) next_ring[lane] = next_w;
@@ -561,21 +569,21 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     work += (int64_t)uniform_sum(stage_work) + (power_ect ? 0 : 3 * os * cnt);
     if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
-    // Completion times back to the jobs; start and machine of every op.
-    for (int k = lane; k < cnt; k += kWave) {
-      const int2 oe = l.op[k];
-      const uint32_t jx = (uint32_t)oe.y;
-      const int e = oe.x;
-      const int end = PLAN ? e & (kMaxTime - 1) : e, mb = PLAN ? e >> 27 : 0;
-      l.rdy[jx >> 20] = end;
-      if (PLAN) {
-        const size_t at = (size_t)(jx & 0xFFFFFu) * I.g + s;
-        const uint32_t pqb = I.pq[((size_t)(jx & 0xFFFFFu) * I.g + s) * I.omp + mb];
-        start_out[at] = end - (int)(pqb & 0xFFFFu);
-        mach_out[at] = mb;
+    // With a plan: start and machine of every op, and the machine bits taken
+    // out of the jobs' completion times.
+    if (PLAN) {
+      for (int k = lane; k < cnt; k += kWave) {
+        const int x = l.op[k];
+        const int e = l.rdy[x];
+        const int end = e & (kMaxTime - 1), mb = e >> 27;
+        const size_t j = (size_t)(l.jobs[x] & 0xFFFFFF);
+        l.rdy[x] = end;
+        const uint32_t pqb = I.pq[(j * I.g + s) * I.omp + mb];
+        start_out[j * I.g + s] = end - (int)(pqb & 0xFFFFu);
+        mach_out[j * I.g + s] = mb;
       }
+      __asm__ volatile("" ::: "memory");
     }
-    __asm__ volatile("" ::: "memory");
   }
   // Objective, eqs. (1)-(3), over every job in J u J'.
   int64_t tard = 0;
@@ -775,11 +783,6 @@ __device__ __forceinline__ int slot_of_block(int b, int K, int islands) {
   return ((t / K) * 8 + xcd) * K + t % K;
 }
 
-// Build the child of slot i for generation gen in l.gene (and store it in
-// A.prio_out): local selection of both parents, neighbour-paired crossover
-// with correction, swap mutation. Crossover and mutation draw from Philox
-// block `variant` (0 for the plain generation; the screened generation's
-// candidates use 0..V-1). Every lane calls this.
 // Build slot i's child in l.gene (and store it in A.prio_out unless !store) from
 // its parent `mine` and, when cross_idx >= 0, the partner parent `other`:
 // slot cross_idx's purpose-1 block decides the crossover (p_c) and its cut, the
@@ -2778,6 +2781,18 @@ int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t
              : FFS_E_DEVICE;
 }
 
+// Single-wave workgroups of the generation kernel that one compute unit holds at
+// `bytes` of LDS each (the runtime's occupancy figure: LDS granularity,
+// registers and wave slots included); 0 if the runtime cannot say.
+template <int MAXM>
+int waves_per_cu(size_t bytes) {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void *)ga_generation_kernel<MAXM>,
+                                                   kWave, bytes) != hipSuccess)
+    return 0;
+  return b;
+}
+
 template <int MAXM>
 int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStream_t stream,
                  bool auto_cap) {
@@ -2809,12 +2824,24 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
              L.hdr) != hipSuccess)
     return FFS_E_DEVICE;
   if (auto_cap) {
-    // later generations keep 5/4 of generation 0's longest schedule + 64 slots on chip
+    // Later generations: generation 0's longest schedule plus 1/16 and 64 slots,
+    // then widened to the most slots (at most the sizing decode's) that keep as
+    // many waves per compute unit.
     Header host;
     if ((rc = read_header(L.hdr, &host, stream))) return rc;
     const int64_t span = host.span_max;
-    const int64_t want = (int64_t)align_up((size_t)(span + span / 4 + 64), 64);
-    ga->lds_slots = (int32_t)(want < cap ? want : cap);
+    int64_t lo = (int64_t)align_up((size_t)(span + span / 16 + 64), 64);
+    if (lo > cap) lo = cap;
+    const int w = waves_per_cu<MAXM>(lds_bytes(n, (int)lo));
+    int64_t a = lo / 64, b = cap / 64;  // waves_per_cu falls as the slots grow
+    while (w > 0 && a < b) {
+      const int64_t m = (a + b + 1) / 2;
+      if (waves_per_cu<MAXM>(lds_bytes(n, (int)(m * 64))) >= w)
+        a = m;
+      else
+        b = m - 1;
+    }
+    ga->lds_slots = (int32_t)(a * 64);
   }
   return FFS_OK;
 }

@@ -171,7 +171,7 @@ def test_ga_is_deterministic():
 def test_ga_auto_sized_profile_changes_nothing():
     """FFS_LDS_AUTO (on-chip slots sized from generation 0's longest schedule)
     gives the same populations as the default slots and the oracle; the chosen
-    slots hold 5/4 of that schedule and stay below the horizon."""
+    slots are a multiple of 64 and stay below the horizon."""
     torch, ffsga = _ffs()
     for cfg, gens in ((1, 12), (2, 20)):
         wl = W.CONFIGS[cfg](2)
