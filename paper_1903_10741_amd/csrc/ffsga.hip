@@ -497,6 +497,10 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const uint32_t next_w = row_word(base + C + lk);  // in flight during this chunk
       const uint32_t *recp = ring + min(lane, os - 1);
       uint32_t pqv = *recp;
+      // Every LDS read before the op loop has landed (lgkmcnt 0): the wait sits
+      // here, and the loop's head, which this read and the op loop's own reads
+      // reach, does not wait for the previous op's profile and end stores.
+      __builtin_amdgcn_s_waitcnt(0xC07F);
       const int k_end = min(base + C, cnt);
     for (int k = base; k < k_end; ++k) {
       opp += 1;
@@ -1330,6 +1334,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
       wsum = (uint64_t)(uint32_t)vz;
       zp = l.zrec + vz;
     }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // as in decode_core_rules: no wait at the loop's head
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
       rec = *++zp;
