@@ -301,6 +301,7 @@ def bench_serve(args):
     counted. With --rates r1,r2,...: a latency-vs-load sweep, the shops split into
     one group per rate (both arrivals of each shop of group k offered at rate k),
     every rate served by the same primed service one after the other."""
+    import dataclasses
     import numpy as np
     import torch
     from paper_1903_10741_amd import autotune, ffsga
@@ -334,6 +335,24 @@ def bench_serve(args):
         curve.append({"offered_per_s": rate, "shops": len(grp), **m})
     need = 1.03e5 * 200   # decodes per request x the workload's 200 requests/s
     last = curve[-1]
+    # roofline of the serving loop's generation kernel: its batch configuration
+    # (slots, profile classes, launch shape) run eagerly with HIP events around every
+    # batched-generation launch, on the shops' current instances
+    rb = ffsga.Batch(dataclasses.replace(srv.cfg, use_graph=False))
+    for k in range(rb.cfg.n_slots):
+        sh = srv.shops[k % len(srv.shops)]
+        rb.set(k, sh.inst, args.seed, sh.sid, sh.event)
+    rb.stream.synchronize()
+    w0 = int(rb.view(0)["work"].item())   # the batch's work counter (all slots)
+    ffsga.timing_enable(True, families=[ffsga.TIMING_BATCH])
+    rgens = 10
+    rb.step(rgens)
+    gen_ms, launches = ffsga.timing_read(ffsga.TIMING_BATCH)
+    ffsga.timing_enable(False)
+    rb.status()
+    work = int(rb.view(0)["work"].item()) - w0
+    avg = gen_ms / 1e3 / max(launches, 1)
+    achieved = work / max(launches, 1) / avg / 1e12
     out = common(args, "exact chromosome decodes/sec", last["decodes_per_s"], "decodes/s",
                  last["wall_s"] * 1e3, "int32", {
                      "workload": f"serving: {len(shops)} shops, {n_arrivals} arrival requests each "
@@ -349,6 +368,13 @@ def bench_serve(args):
                      "curve": curve})
     out["steps"] = 1
     out["warmup"] = 0
+    out["roofline"] = {"bound": "alu", "kernel": f"batch_generation_kernel (serving batch: "
+                                                 f"{rb.cfg.n_slots} slots x {rb.pop})",
+                       "achieved": achieved, "peak": VALU_INT32_PEAK_TOPS, "unit": "TOP/s int32",
+                       "frac": achieved / VALU_INT32_PEAK_TOPS, "traffic": None,
+                       "avg_launch_us": avg * 1e6, "launches": launches,
+                       "work_per_decode": work / max(rb.cfg.n_slots * rb.pop * rgens, 1),
+                       "build_id": ffsga.ffs_build_id()}
     return out
 
 

@@ -281,16 +281,18 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //   jobs  [n+1]      by rank: job | first_stage << 24  (correction scratch before decode)
 //   rdy   [n+1]      by rank: completion of the job's last placed stage (scratch before);
 //                    an op's end replaces it as soon as the op is placed
-//   op    [n+2]      the current stage's ops in order, as ranks (two spare records that
-//                    the op loop prefetches past the last)
-//   gene  [n]        the chromosome (input), in op's region: it is dead once the decode
-//                    has built the ranks, before any op record
+//   op    [n+2]      the current stage's ops in order, as 16-bit ranks (two spare
+//                    records that the op loop prefetches past the last)
 //   rec   [2][kRing] packed P | Q << 16 rows of the stage's ops, one word per machine,
 //                    staged from the packed table kWave / o_s ops at a time, double buffered
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
+//   gene  [n]        the chromosome (input), at the start of prof's region (which holds
+//                    at least n words): it is dead once the decode has built the ranks,
+//                    before the profile is cleared
 struct Lds {
-  int32_t *gene, *jobs, *rdy, *op;
+  int32_t *gene, *jobs, *rdy;
+  uint16_t *op;
   uint32_t *rec;
   uint8_t *prof;
 };
@@ -299,9 +301,14 @@ struct Lds {
 // plus the record the op loop prefetches one past the chunk (read, never used).
 constexpr int kRing = kWave + 16;
 
+// LDS bytes before the profile region, and in all (cap = 0: no on-chip profile,
+// the region still holds the genes).
+__host__ __device__ inline size_t lds_head(int n) {
+  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)2 * n + 4, 16) + 8 * kRing;
+}
 __host__ __device__ inline size_t lds_bytes(int n, int cap) {
-  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)4 * n + 8, 16) + 8 * kRing +
-         (cap > 0 ? align_up(cap, 16) + kWave : 0);
+  const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0, gene = align_up((size_t)4 * n, 16);
+  return lds_head(n) + (prof > gene ? prof : gene);
 }
 
 __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
@@ -309,10 +316,10 @@ __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   const size_t a = align_up((size_t)4 * n + 4, 16);
   l.jobs = (int32_t *)smem;
   l.rdy = (int32_t *)(smem + a);
-  l.op = (int32_t *)(smem + 2 * a);
-  l.gene = l.op;
-  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)4 * n + 8, 16));
+  l.op = (uint16_t *)(smem + 2 * a);
+  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)2 * n + 4, 16));
   l.prof = (uint8_t *)l.rec + 8 * kRing;
+  l.gene = (int32_t *)l.prof;
   return l;
 }
 
@@ -447,7 +454,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
             k += (l.jobs[y] >> 24) <= s && (cy < cx || (cy == cx && y < x));
           }
         }
-        l.op[k] = x;
+        l.op[k] = (uint16_t)x;
       }
       cnt += __popcll(mk);
     }
@@ -479,7 +486,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     // per stage) one op ahead, and writes each op's end into rdy at once.
     int vz;
     __asm__("v_mov_b32 %0, 0" : "=v"(vz));
-    const int32_t *opp = l.op + vz;
+    const uint16_t *opp = l.op + vz;
     int32_t *rdy_at = l.rdy + opp[0];  // the current op's job
     int rk1 = opp[1];                  // the next op's rank
     int ex = *rdy_at;                  // the current op's job's ready time
@@ -2713,7 +2720,7 @@ int layout_cap(const ffs_ga_params *p, int cap) { return p->lds_slots == FFS_LDS
 constexpr int64_t kProbeSlots = 32768;
 int probe_cap(const ffs_instance *in) {
   const int64_t h = (int64_t)align_up((size_t)in->horizon, 64);
-  const int64_t room = (int64_t)max_lds_bytes() - (int64_t)lds_bytes(in->n_active, 0) - kWave;
+  const int64_t room = (int64_t)max_lds_bytes() - (int64_t)lds_head(in->n_active) - kWave;
   int64_t cap = room / 64 * 64;
   if (cap > kProbeSlots) cap = kProbeSlots;
   if (cap > h) cap = h;
