@@ -283,8 +283,8 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //                    an op's end replaces it as soon as the op is placed
 //   op    [n+2]      the current stage's ops in order, as 16-bit ranks (two spare
 //                    records that the op loop prefetches past the last)
-//   rec   [2][kRing] packed P | Q << 16 rows of the stage's ops, one word per machine,
-//                    staged from the packed table kWave / o_s ops at a time, double buffered
+//   rec   [kRing]    packed P | Q << 16 rows of the stage's ops, one word per machine,
+//                    staged from the packed table kWave / o_s ops at a time
 //   prof  [cap+64]   power in use per time slot after RS, one byte per slot (the last
 //                    64 stay zero so a chunk read never needs clamping)
 //   gene  [n]        the chromosome (input), at the start of prof's region (which holds
@@ -304,7 +304,7 @@ constexpr int kRing = kWave + 16;
 // LDS bytes before the profile region, and in all (cap = 0: no on-chip profile,
 // the region still holds the genes).
 __host__ __device__ inline size_t lds_head(int n) {
-  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)2 * n + 4, 16) + 8 * kRing;
+  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)2 * n + 4, 16) + 4 * kRing;
 }
 __host__ __device__ inline size_t lds_bytes(int n, int cap) {
   const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0, gene = align_up((size_t)4 * n, 16);
@@ -318,7 +318,7 @@ __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   l.rdy = (int32_t *)(smem + a);
   l.op = (uint16_t *)(smem + 2 * a);
   l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)2 * n + 4, 16));
-  l.prof = (uint8_t *)l.rec + 8 * kRing;
+  l.prof = (uint8_t *)l.rec + 4 * kRing;
   l.gene = (int32_t *)l.prof;
   return l;
 }
@@ -462,9 +462,10 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     __asm__ volatile("" ::: "memory");
     // The ops' packed P|Q rows come from the packed table chunk by chunk: lane
     // lk * o_s + lm holds machine lm of op lk of a chunk of kWave / o_s ops.
-    // The rows of chunk c + 1 are loaded while chunk c runs and stored into the
-    // other ring buffer when it ends, so the loads' latency stays hidden and
-    // LDS holds two chunks instead of the whole stage.
+    // The rows of chunk c + 1 are loaded while chunk c runs and stored over
+    // chunk c's when it ends (after its last read: LDS keeps a wave's order),
+    // so the loads' latency stays hidden and LDS holds one chunk instead of the
+    // whole stage.
     const int C = kWave / os, lk = lane / os, lm = lane - lk * os;
     const uint32_t *pq_stage = I.pq + (size_t)s * I.omp + lm;
     const size_t pq_job = (size_t)I.g * I.omp;
@@ -498,11 +499,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     // right per op, over the same slots again for later ops: 64 bits.
     using StageWork = typename std::conditional<RULES, u64, uint32_t>::type;
     StageWork stage_work = (StageWork)(uint32_t)vz;
-    for (int base = 0, c = 0; base < cnt; base += C, ++c) {
-      const uint32_t *ring = l.rec + (c & 1) * kRing;
-      uint32_t *next_ring = l.rec + (1 - (c & 1)) * kRing;
+    for (int base = 0; base < cnt; base += C) {
       const uint32_t next_w = row_word(base + C + lk);  // in flight during this chunk
-      const uint32_t *recp = ring + min(lane, os - 1);
+      const uint32_t *recp = l.rec + min(lane, os - 1);
       uint32_t pqv = *recp;
       // Every LDS read before the op loop has landed (lgkmcnt 0): the wait sits
       // here, and the loop's head, which this read and the op loop's own reads
@@ -574,7 +573,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       ex = ex_next;
       pqv = pq_next;
     }
-      if (lk < C) next_ring[lane] = next_w;
+      if (lk < C) l.rec[lane] = next_w;
       __asm__ volatile("" ::: "memory");
     }
     work += (int64_t)uniform_sum(stage_work) + (power_ect ? 0 : 3 * os * cnt);
