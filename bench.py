@@ -180,17 +180,18 @@ def cpu_model():
 
 
 def profile_figures(kname, workload):
-    """HBM bytes and VALU issue per launch from the rocprofv3 counter runs committed
-    under profiles/, used only when they were taken on this very build."""
+    """HBM bytes per launch, VALU issue rate and VALU lane utilisation from the
+    rocprofv3 counter runs committed under profiles/, used only when they were
+    taken on this very build: (traffic, issue TOP/s, lane utilisation)."""
     from paper_1903_10741_amd import ffsga
     tpath = os.path.join(ROOT, "profiles", f"{kname}_{workload}.traffic.json")
     if not os.path.exists(tpath):
-        return None, None
+        return None, None, None
     t = json.load(open(tpath))
     if t.get("build_id") != ffsga.ffs_build_id():
-        return None, None
+        return None, None, None
     return (t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"],
-            t.get("valu_issue_tlops"))
+            t.get("valu_issue_tlops"), t.get("valu_lane_utilisation"))
 
 
 def bench_large(args):
@@ -254,7 +255,7 @@ def bench_large(args):
     work_per_decode = work / max(ga_decodes, 1)
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
     achieved = work_per_decode * wl.ga.pop / avg_launch_s / 1e12
-    traffic, valu_issue = profile_figures("ga_generation_kernel", "large-200x10x4-6")
+    traffic, valu_issue, lane_util = profile_figures("ga_generation_kernel", "large-200x10x4-6")
     best = {}
     for ev in events:
         best.setdefault(ev.event, int(ev.best_obj.item()))
@@ -283,6 +284,7 @@ def bench_large(args):
         "frac": achieved / VALU_INT32_PEAK_TOPS,
         "traffic": traffic,
         "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
+        "valu_lane_utilisation": lane_util,
         "work_per_decode": work_per_decode,
         "decodes_per_launch": wl.ga.pop,
         "avg_launch_us": avg_launch_s * 1e6,
@@ -902,7 +904,7 @@ def bench_paper(args, steps, warmup):
     work_per_decode = sum(int(e.work.item()) for e in res.events) / max(res.ga_decodes, 1)
 
     kname = "ga_generation_xy_kernel" if xy else "ga_generation_kernel"
-    traffic, valu_issue = profile_figures(kname, "paper-50x5x3")
+    traffic, valu_issue, lane_util = profile_figures(kname, "paper-50x5x3")
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
     achieved = work_per_decode * wl.ga.pop / avg_launch_s / 1e12
     out = common(args, "exact chromosome decodes/sec", decodes / elapsed, "decodes/s",
@@ -927,6 +929,7 @@ def bench_paper(args, steps, warmup):
         "frac": achieved / VALU_INT32_PEAK_TOPS,
         "traffic": traffic,
         "valu_issue_frac": (valu_issue / VALU_INT32_PEAK_TOPS) if valu_issue else None,
+        "valu_lane_utilisation": lane_util,
         "work_per_decode": work_per_decode,
         "decodes_per_launch": wl.ga.pop,
         "avg_launch_us": avg_launch_s * 1e6,

@@ -73,6 +73,21 @@ def test_decode_ragged_gene_counts(n):
     _compare(inst, W.random_population(n, 16, n))
 
 
+def test_decode_max_gene_count():
+    """n_active = 4096, the largest the ABI takes: 16-bit op records hold ranks up to
+    4095; the default 4096 on-chip slots overflow, so the decodes go off chip."""
+    torch, ffsga = _ffs()
+    _say("decode at n = 4096")
+    inst = W.random_instance(7, n_jobs=4096, n_stages=2, machines=[3, 2], p_max=6, q_range=(1, 5),
+                             percent=60)
+    _compare(inst, W.random_population(7, 3, 4096), schedule=False)
+    _compare(inst, W.random_population(8, 2, 4096), lds_slots=32768)
+    big = W.random_instance(7, n_jobs=4097, n_stages=1, machines=2, p_max=3)
+    with pytest.raises(ffsga.FfsError) as e:
+        ffsga.DeviceInstance.from_host(big)
+    assert e.value.code == ffsga.FFS_E_UNSUPPORTED
+
+
 def test_decode_long_windows_span_several_chunks():
     _say("decode with p up to 200 (windows of 4 chunks)")
     inst = W.random_instance(5, n_jobs=20, n_stages=4, machines=[3, 5, 2, 4], p_max=200,
