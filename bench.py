@@ -26,8 +26,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 64 int32 lanes per clock x 2.4 GHz
-VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 256 CUs x 128 int32 lanes per clock (4 SIMDs x 32) x 2.4 GHz: the fp32 vector
+# figure, 157.3 TFLOP/s, counts an FMA as two FLOP, i.e. 78.6 T lane-FMAs/s; int32
+# adds issue at that rate too (measure_peaks reaches 66 T at 8 waves per SIMD, more
+# than 64 lanes per clock per CU allow)
+VALU_INT32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
@@ -142,7 +145,7 @@ def bench_batch(args):
     return out
 
 
-def oracle_rate_large(wl, gens=10):
+def oracle_rate_large(wl, gens=20):
     """The CPU oracle on event 0 of the large workload: init + `gens` generations of
     the whole population (OpenMP over the population, all host threads), and one
     thread on a bounded sample of random priority vectors."""
@@ -746,7 +749,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
                     choices=["large", "paper", "batch", "serve", "surrogate", "rs-ratio",
-                             "schemes"],
+                             "schemes", "peaks"],
                     help="large (default): the large-200x10x4-6 event loop, one event per step, "
                          "with the paper-shaped workload measured beside it")
     ap.add_argument("--lds-slots", type=int, default=0)
@@ -811,6 +814,13 @@ def main():
     if args.workload == "schemes":
         print(json.dumps(bench_schemes(args)), flush=True)
         return
+    if args.workload == "peaks":
+        pk = measure_peaks()
+        print(json.dumps(common(args, "measured int32 VALU rate", pk["valu_int32_tops"],
+                                "T lane-ops/s", None, "int32",
+                                {"workload": "device peaks: int32 vector adds, bf16 matrix-core "
+                                             "products, device-to-device copy", **pk})), flush=True)
+        return
     if args.workload == "paper":
         out = bench_paper(args, args.steps, args.warmup)
         if not args.no_cpu_baseline:
@@ -846,7 +856,44 @@ def main():
         from paper_1903_10741_amd import workloads as W
         progress("CPU oracle (large workload, event 0)")
         out["cpu_baseline"] = oracle_rate_large(W.config3(args.seed))
+        progress("device peaks")
+        out["measured_peaks"] = measure_peaks()
     print(json.dumps(out), flush=True)
+
+
+def measure_peaks():
+    """The rates the rooflines divide by, measured on this GPU: int32 vector adds
+    (8 independent chains per lane, 1-32 blocks of 4 waves per CU), bf16
+    matrix-core products (v_mfma_f32_32x32x16_bf16, 4 independent accumulators per
+    wave, 1-16 blocks per CU) and a 2 GiB device-to-device copy (read + write
+    bytes). The best rate of each sweep is reported beside the sweep."""
+    import torch
+    from paper_1903_10741_amd import peaks
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    peaks.ffs_peak_valu_int32(8 * n_cu, 64)
+    valu = [(k, peaks.ffs_peak_valu_int32(k * n_cu, 1000)[1] / 1e12) for k in (1, 2, 4, 8, 16, 32)]
+    peaks.ffs_peak_mfma_bf16(4 * n_cu, 8)
+    mfma = [(k, peaks.ffs_peak_mfma_bf16(k * n_cu, 200)[1] / 1e12) for k in (1, 2, 4, 8, 16)]
+    n = 1 << 29
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_s = e0.elapsed_time(e1) / 1e3 / 5
+    del src, dst
+    hbm = 2 * n * 4 / copy_s / 1e9
+    v_best, m_best = max(r for _, r in valu), max(r for _, r in mfma)
+    return {"valu_int32_tops": v_best, "valu_frac_of_peak": v_best / VALU_INT32_PEAK_TOPS,
+            "valu_by_blocks_per_cu": {str(k): r for k, r in valu},
+            "mfma_bf16_tflops": m_best, "mfma_frac_of_2500": m_best / 2500.0,
+            "mfma_by_blocks_per_cu": {str(k): r for k, r in mfma},
+            "hbm_copy_gbs": hbm, "hbm_frac_of_8000": hbm / HBM_PEAK_GBS,
+            "compute_units": n_cu}
 
 
 def copy_calibration(args):

@@ -26,15 +26,25 @@ def build_id() -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False, extra=()) -> str:
+# The device-peak measurements (include/ffs_peaks.h), a library of their own so
+# that the decoder's build id does not depend on them.
+PEAKS_LIB = os.path.join(HERE, "libffspeaks.so")
+PEAKS_SRC = os.path.join(HERE, "csrc", "peaks.hip")
+
+
+def _compile(out, srcs, extra, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, f'-DFFS_BUILD_ID="{build_id()}"', "-I", INCLUDE, "-o", tmp,
-           *SRCS]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    _compile(LIB, SRCS, [*extra, f'-DFFS_BUILD_ID="{build_id()}"'], verbose)
+    _compile(PEAKS_LIB, [PEAKS_SRC], list(extra), verbose)
     return LIB
 
 

@@ -1,6 +1,8 @@
-"""The C-ABI library loads and exports every entry point include/ffsga.h declares.
+"""The C-ABI libraries load and export every entry point their headers declare:
+include/ffsga.h and include/ffs_surrogate.h for libffsga.so, include/ffs_peaks.h
+for libffspeaks.so.
 
-Runs without a GPU: loading the library does not touch the device.
+Runs without a GPU: loading a library does not touch the device.
 """
 import ctypes
 import os
@@ -10,12 +12,19 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1903_10741_amd", "libffsga.so")
+PEAKS_LIB = os.path.join(ROOT, "paper_1903_10741_amd", "libffspeaks.so")
+PEAKS_HEADERS = ("ffs_peaks.h",)
 
 
-def declared_functions():
+def test_every_header_belongs_to_a_library():
+    headers = {n for n in os.listdir(os.path.join(ROOT, "include")) if n.endswith(".h")}
+    assert headers == {"ffsga.h", "ffs_surrogate.h", *PEAKS_HEADERS}
+
+
+def declared_functions(peaks=False):
     names = []
     for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
-        if not name.endswith(".h"):
+        if not name.endswith(".h") or (name in PEAKS_HEADERS) != peaks:
             continue
         text = open(os.path.join(ROOT, "include", name)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -41,6 +50,17 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_the_abi():
     from paper_1903_10741_amd import ffsga
     assert set(ffsga.exported_symbols()) == set(declared_functions())
+
+
+def test_peaks_library_exports_its_header():
+    if not os.path.exists(PEAKS_LIB):
+        pytest.fail("libffspeaks.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(PEAKS_LIB)
+    names = declared_functions(peaks=True)
+    assert names == ["ffs_peak_mfma_bf16", "ffs_peak_valu_int32"]
+    assert all(hasattr(lib, n) for n in names)
+    from paper_1903_10741_amd import peaks
+    assert set(peaks.exported_symbols()) == set(names)
 
 
 def test_strerror_is_host_only():
