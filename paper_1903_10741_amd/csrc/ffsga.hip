@@ -499,6 +499,11 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     // right per op, over the same slots again for later ops: 64 bits.
     using StageWork = typename std::conditional<RULES, u64, uint32_t>::type;
     StageWork stage_work = (StageWork)(uint32_t)vz;
+    // Each op's profile update is issued by the next op, after its machine choice
+    // and before its first profile read: the update's vector work then fills the
+    // machine choice's dependency gaps instead of lengthening the op's chain. The
+    // stage's first op updates an empty window (p = 0 adds nothing).
+    int ct = 0, cp = 0, cq = 0;
     for (int base = 0; base < cnt; base += C) {
       const uint32_t next_w = row_word(base + C + lk);  // in flight during this chunk
       const uint32_t *recp = l.rec + min(lane, os - 1);
@@ -524,6 +529,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       int t = 0;
       StageWork cw = 0;
       if (power_ect) {
+        prof.commit(ct, cp, cq);  // the previous op of the stage
         // FFS_RULE_POWER_ECT: the earliest completion after the machine's push-right
         // (ties to the lowest index). The key above, (completion ignoring power) << 4
         // | machine, bounds a machine's key after its push-right from below: the
@@ -558,12 +564,15 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // Q > Q_max is rejected by the instance checks; even then the unsigned
         // threshold only makes every slot pass, so the push-right still ends.
         const int t0 = __builtin_amdgcn_readlane(t0v, mb);
+        prof.commit(ct, cp, cq);  // the previous op of the stage
         t = prof.place(t0, p, (uint32_t)(I.q_max - q));
         cw = (StageWork)((t - t0) + 2 * p);
       } else {
         cw += (StageWork)p;
       }
-      prof.commit(t, p, q);
+      ct = t;
+      cp = p;
+      cq = q;
       const int end = t + p + rs;
       fr = ffs_writelane(end, mb, fr);
       *rdy_at = PLAN ? end | (mb << 27) : end;
@@ -576,6 +585,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       if (lk < C) l.rec[lane] = next_w;
       __asm__ volatile("" ::: "memory");
     }
+    prof.commit(ct, cp, cq);  // the stage's last op
     work += (int64_t)uniform_sum(stage_work) + (power_ect ? 0 : 3 * os * cnt);
     if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
