@@ -1351,6 +1351,8 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
       zp = l.zrec + vz;
     }
     __builtin_amdgcn_s_waitcnt(0xC07F);  // as in decode_core_rules: no wait at the loop's head
+    // each op's profile update issued by the next op, as in decode_core_rules
+    int ct = 0, cp = 0, cq = 0;
     for (int z = 0; z < R; ++z) {
       const int xf = uni(rec.x), x = xf & 0xFFF, f = xf >> 12, pqw = uni(rec.y);
       rec = *++zp;
@@ -1362,8 +1364,11 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
       const int est = max(rs, hi ? r1 : r0), fr = __builtin_amdgcn_readlane(fmv, f);
       const int p = pqw & 0xFFFF, q = (int)((uint32_t)pqw >> 16);
       const int t0 = max(est, fr) - rs;
+      prof.commit(ct, cp, cq);
       const int t = prof.place(t0, p, (uint32_t)(I.q_max - q));
-      prof.commit(t, p, q);
+      ct = t;
+      cp = p;
+      cq = q;
       const int end = t + p + rs;
       rv0 = ffs_writelane(hi ? r0 : end, xl, rv0);
       if (NB > 1) rv1 = ffs_writelane(hi ? end : r1, xl, rv1);
@@ -1376,6 +1381,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
         mach_out[(size_t)j * I.g + s] = f - s * I.om;
       }
     }
+    prof.commit(ct, cp, cq);
     work = (int64_t)(((uint64_t)(uint32_t)uni((int)(uint32_t)(wsum >> 32)) << 32) |
                      (uint32_t)uni((int)(uint32_t)wsum));
     if (lane < n) l.rdy[lane] = rv0;
