@@ -249,17 +249,29 @@ __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint
 // add zero: cheaper than testing for it). Slots past cap (the
 // decode is then redone off chip) are clamped onto the last word, so the zero
 // slots after cap stay zero.
-template <class Prof>
-__device__ __forceinline__ void commit_bytes(const Prof &prof, int t, int p, int q) {
-  const int lane = __lane_id(), cap = prof.cap;
+//
+// In two halves: commit_word forms each quad's word increment (registers only),
+// commit_add adds them; an op loop can place independent work between the two.
+__device__ __forceinline__ uint32_t commit_word(int t, int p, int q) {
+  const int lane = __lane_id();
   const int base = t & ~3;
   uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
   c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
   c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0x4E, 0xF, 0xF, false);
+  return c;
+}
+template <class Prof>
+__device__ __forceinline__ void commit_add(const Prof &prof, int t, int p, int q, uint32_t c) {
+  const int lane = __lane_id(), cap = prof.cap;
+  const int base = t & ~3;
   if ((lane & 3) == 0) prof.add_word(min(base + lane, cap - 4), c);
   if (t - base + p > kWave)  // windows longer than the lanes
     for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
   prof.order();
+}
+template <class Prof>
+__device__ __forceinline__ void commit_bytes(const Prof &prof, int t, int p, int q) {
+  commit_add(prof, t, p, q, commit_word(t, p, q));
 }
 
 __device__ __forceinline__ int LdsProfile::place(int t0, int p, uint32_t thr) const {
@@ -520,6 +532,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       int32_t *const rdy_next = l.rdy + rk1;
       const int ex_next = *rdy_next;
       const uint32_t pq_next = *recp;
+      // the previous op's profile words, formed while this op's keys reduce
+      const uint32_t cword = commit_word(ct, cp, cq);
       // Machine of earliest completion (ties to the lowest index).
       const int mx = max(max(ex, rs), fr);
       const int t0v = mx - rs;  // earliest start on this lane's machine, slots after RS
@@ -564,7 +578,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // Q > Q_max is rejected by the instance checks; even then the unsigned
         // threshold only makes every slot pass, so the push-right still ends.
         const int t0 = __builtin_amdgcn_readlane(t0v, mb);
-        prof.commit(ct, cp, cq);  // the previous op of the stage
+        commit_add(prof, ct, cp, cq, cword);  // the previous op of the stage
         t = prof.place(t0, p, (uint32_t)(I.q_max - q));
         cw = (StageWork)((t - t0) + 2 * p);
       } else {
