@@ -348,6 +348,20 @@ __device__ __forceinline__ uint32_t machine_min(uint32_t v) {
   return v;
 }
 
+// The same minimum as a scalar: up to 4 machines one readlane of the quad
+// minimum; 8 the smaller of two quads' minima read out (two readlanes and a
+// scalar min instead of a third DPP step and its wait states).
+template <int MAXM>
+__device__ __forceinline__ uint32_t machine_min_scalar(uint32_t v) {
+  if (MAXM == 8) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, 0x4E, 0xF, 0xF, false));
+    return min((uint32_t)__builtin_amdgcn_readlane((int)v, 3),
+               (uint32_t)__builtin_amdgcn_readlane((int)v, 7));
+  }
+  return (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(v), MAXM - 1);
+}
+
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
@@ -538,8 +552,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       const int mx = max(max(ex, rs), fr);
       const int t0v = mx - rs;  // earliest start on this lane's machine, slots after RS
       const uint32_t key = ((uint32_t)(mx + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
-      uint32_t kmin =
-          (uint32_t)__builtin_amdgcn_readlane((int)machine_min<MAXM>(key), MAXM - 1);
+      uint32_t kmin = machine_min_scalar<MAXM>(key);
       int t = 0;
       StageWork cw = 0;
       if (power_ect) {
