@@ -244,6 +244,8 @@ typedef struct {
   int64_t *obj[2];                  /* device [pop] */
   int32_t *elite;                   /* device [islands][n_genes] */
   int64_t *elite_obj;               /* device [islands] */
+  int32_t island_groups;            /* island groups the last ga_step ran (1: one stream,
+                                       0: none yet; ga_set_island_groups) */
 } ffs_ga;
 
 /* Device views of a GA state (pointers into its workspace). */
@@ -279,6 +281,25 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
  * the results are the same either way.
  * Errors: FFS_E_INVAL, FFS_E_DEVICE. */
 int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream);
+
+/* How many island groups ga_step runs concurrently (process-wide; 0, the
+ * default, means 4; 1 runs every launch on the caller's stream). Between two
+ * migrations the islands of the hybrid GA (Section 4.4) share nothing, so
+ * ga_step splits them into `groups` contiguous groups (group g: islands
+ * [islands * g / groups, islands * (g + 1) / groups)) and runs each group's
+ * generations on a stream of its own: a group that has decoded and replaced
+ * its islands starts its next generation while others still decode. The
+ * library creates the extra streams (default priority) and events once per
+ * device; they fork from the caller's stream, and ga_step joins them back into
+ * it before every migration and before it returns, so the caller's stream
+ * orders everything as before. Results are the same for every grouping (draws
+ * are keyed by the global slot). Grouping applies to the hybrid scheme whose
+ * overflowed decodes are redone by their own waves (see ga_step), not to
+ * ga_step_screened or the comparison GAs, and never to more groups than
+ * islands. Calls of ga_step from several host threads take turns enqueueing
+ * on one device while grouping is in use.
+ * Errors: FFS_E_INVAL (groups < 0 or > 4). */
+int ga_set_island_groups(int32_t groups);
 
 /* Copy the best elite (lowest island on ties) to prio_out (device
  * [n_genes]) and obj_out (device int64 [1]). */
@@ -406,16 +427,20 @@ int ga_batch_destroy(ffs_batch *b);
  * 0 = decode (ffs_decode), 1 = GA generation (breed + decode), 2 = GA
  * replacement, 3 = overflow decode, 4 = batched generation (breed + decode,
  * outside graphs), 5 = screened generation (ffs_surrogate.h: candidate
- * breeding + scoring + decode). families: 0 stops timing; otherwise bit f
- * selects family f (-1: all) and every family's count starts afresh. Only the
- * selected families get events, so untimed launches carry no event overhead.
- * ffs_timing_read synchronises and returns the summed kernel time and the
- * number of launches since the call. */
+ * breeding + scoring + decode). Family 6 times whole ga_step calls instead:
+ * events on the caller's stream before its first launch and after its last
+ * (island groups joined), every call, counted in generations, so its time over
+ * its count is the time per generation of the whole population even when
+ * island groups overlap their launches. families: 0 stops timing; otherwise
+ * bit f selects family f (-1: all) and every family's count starts afresh.
+ * Only the selected families get events, so untimed launches carry no event
+ * overhead. ffs_timing_read synchronises and returns the summed time and the
+ * number of launches (family 6: generations) since the call. */
 int ffs_timing_enable(int32_t families);
 
-/* Put events on one launch in `every` (>= 1, default 1) of each timed family,
- * starting with the first after ffs_timing_enable; ffs_timing_read then counts
- * the timed launches only. Errors: FFS_E_INVAL. */
+/* Put events on one launch in `every` (>= 1, default 1) of each timed kernel
+ * family (0-5), starting with the first after ffs_timing_enable;
+ * ffs_timing_read then counts the timed launches only. Errors: FFS_E_INVAL. */
 int ffs_timing_every(int32_t every);
 int ffs_timing_read(int32_t family, double *total_ms, int64_t *launches);
 

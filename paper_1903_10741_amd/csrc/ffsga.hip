@@ -26,6 +26,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -220,7 +221,9 @@ struct GlobalProfile {
 // [scan, scan + 64); a ballot marks the window's slots that break the peak and
 // t jumps past the last of them, re-testing the same chunk; a clean window
 // part that runs off the chunk moves on to the next 64 slots. Reads past cap
-// land in the 64 zero slots after it.
+// land in the 64 zero slots after it. The re-tests form an inner loop and the
+// branches carry the common case's odds (no slot breaks the peak, the window
+// ends in the first chunk), so that case runs straight through.
 template <class Prof>
 __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint32_t thr) {
   const int lane = __lane_id(), cap = prof.cap;
@@ -229,12 +232,12 @@ __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint
   uint32_t v = prof.get(sl);
   for (;;) {
     // slots of [t, t + p) in this chunk (one unsigned compare) that break the peak
-    const u64 hit = ballot64((uint32_t)(sl - t) < (uint32_t)p) & ballot64(v > thr);
-    if (hit) {
+    u64 hit = ballot64((uint32_t)(sl - t) < (uint32_t)p) & ballot64(v > thr);
+    while (__builtin_expect(hit != 0, 0)) {
       t = top - (int)__clzll(hit);
-      continue;
+      hit = ballot64((uint32_t)(sl - t) < (uint32_t)p) & ballot64(v > thr);
     }
-    if (t + p <= top || top >= cap) break;
+    if (__builtin_expect(t + p <= top || top >= cap, 1)) break;
     top += kWave;
     sl += kWave;
     v = prof.get(sl);
@@ -265,7 +268,7 @@ __device__ __forceinline__ void commit_add(const Prof &prof, int t, int p, int q
   const int lane = __lane_id(), cap = prof.cap;
   const int base = t & ~3;
   if ((lane & 3) == 0) prof.add_word(min(base + lane, cap - 4), c);
-  if (t - base + p > kWave)  // windows longer than the lanes
+  if (__builtin_expect(t - base + p > kWave, 0))  // windows longer than the lanes
     for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
   prof.order();
 }
@@ -760,7 +763,9 @@ struct GaDev {
   uint8_t *redo_prof;
   size_t redo_stride;
   u64 seed, shop;
-  int32_t event, rows, cols, islands, mig_k;
+  // islands: the islands a generation launch covers, from island isl0 on (the
+  // whole population but for ga_step's island groups)
+  int32_t event, rows, cols, islands, mig_k, isl0;
   uint32_t pc, pm;
 };
 
@@ -1181,7 +1186,7 @@ template <int MAXM>
 __global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int gen, int cap) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = A.rows * A.cols;
-  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const int i = A.isl0 * K + slot_of_block(blockIdx.x, K, A.islands);
   const Lds l = carve_lds(smem, I.n);
   breed_child(A, I.n, i, gen, l);
   decode_and_record<MAXM>(I, A, i, cap, l, i);
@@ -1723,7 +1728,7 @@ __global__ __launch_bounds__(64) void ga_generation_xy_kernel(DInst I, XyTab T, 
                                                               int cap) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = A.rows * A.cols;
-  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const int i = A.isl0 * K + slot_of_block(blockIdx.x, K, A.islands);
   const LdsXy l = carve_lds_xy(smem, I.n, T.R, I.g, I.om);
   breed_child_xy(A, I, T, i, gen, l);
   decode_and_record_xy(I, T, A, i, cap, l);
@@ -2022,6 +2027,7 @@ __device__ __forceinline__ GaDev slot_ga(const BatchSlot &S, const BatchArgs &B,
   A.rows = B.rows;
   A.cols = B.cols;
   A.islands = B.islands;
+  A.isl0 = 0;
   A.mig_k = B.mig_k;
   A.pc = B.pc;
   A.pm = B.pm;
@@ -2468,7 +2474,8 @@ __global__ __launch_bounds__(1024) void reschedule_kernel(ReschedArgs a, Header 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-constexpr int kTimingFamilies = 6;
+constexpr int kTimingFamilies = 7;
+constexpr int kTimingStep = 6;  // ga_step spans, counted in generations
 struct Timing {
   std::mutex mu;
   bool on = false;
@@ -2511,6 +2518,27 @@ hipError_t launch(int family, K kernel, dim3 grid, dim3 block, size_t shmem, hip
     hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
   }
   return hipGetLastError();
+}
+
+// Events around a whole ga_step call on the caller's stream (kTimingStep): the
+// span from before its first launch to after its island groups are joined.
+// Returns the event pair's index, or -1 when the family is not timed.
+int span_begin(hipStream_t s) {
+  if (!g_timing.on || !((g_timing.mask >> kTimingStep) & 1u)) return -1;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  if (g_timing.used[kTimingStep] == kTimingPairs) {
+    drain_family(kTimingStep, kTimingPairs);
+    g_timing.used[kTimingStep] = 0;
+  }
+  const int k = (int)g_timing.used[kTimingStep]++;
+  (void)hipEventRecord(g_timing.ev[kTimingStep][2 * k], s);
+  return k;
+}
+void span_end(int k, hipStream_t s, int64_t generations) {
+  if (k < 0) return;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  (void)hipEventRecord(g_timing.ev[kTimingStep][2 * k + 1], s);
+  g_timing.launches[kTimingStep] += generations;
 }
 
 int max_lds_bytes() {
@@ -2802,6 +2830,7 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
   A.rows = ga->params.rows;
   A.cols = ga->params.cols;
   A.islands = ga->params.islands;
+  A.isl0 = 0;
   A.mig_k = ga->params.mig_k;
   A.pc = ga->params.pc;
   A.pm = ga->params.pm;
@@ -2900,6 +2929,63 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
   return FFS_OK;
 }
 
+constexpr int kMaxDevices = 64;
+
+// Island groups of ga_step. Between two migrations the islands of a GA share
+// nothing, so ga_step can run groups of islands on streams of their own: a group
+// that has decoded its slowest chromosome and replaced its islands starts its
+// next generation while the other groups still decode, and the compute units
+// stay busy through each launch's tail instead of waiting at a barrier over the
+// whole population. Every draw is keyed by the global slot, so the results do
+// not depend on the grouping. Group 0 runs on the caller's stream; groups 1..
+// run on per-device streams of this library (default priority, not blocking
+// the null stream), forked from and joined back into the caller's stream with
+// events, before and after every migration and at the end of the call.
+constexpr int kMaxGroups = 4;
+std::atomic<int> g_island_groups{0};  // 0: automatic (kMaxGroups)
+
+struct GroupStreams {
+  hipStream_t s[kMaxGroups] = {};  // s[0] stays null: group 0 is the caller's stream
+  hipEvent_t fork = nullptr, join[kMaxGroups] = {};
+  bool ready = false;
+};
+// Held across a grouped ga_step's launches: two host threads would otherwise
+// re-record one fork or join event between another's record and wait.
+std::mutex g_group_mu;
+GroupStreams g_groups[kMaxDevices];
+
+void release_groups(GroupStreams &G) {
+  for (int g = 1; g < kMaxGroups; ++g) {
+    if (G.s[g]) (void)hipStreamDestroy(G.s[g]);
+    if (G.join[g]) (void)hipEventDestroy(G.join[g]);
+    G.s[g] = nullptr;
+    G.join[g] = nullptr;
+  }
+  if (G.fork) (void)hipEventDestroy(G.fork);
+  G.fork = nullptr;
+}
+
+// This device's group streams and events, created on first use (the caller
+// holds g_group_mu).
+int group_streams(GroupStreams **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FFS_E_DEVICE;
+  GroupStreams &G = g_groups[dev];
+  if (!G.ready) {
+    bool ok = hipEventCreateWithFlags(&G.fork, hipEventDisableTiming) == hipSuccess;
+    for (int g = 1; ok && g < kMaxGroups; ++g)
+      ok = hipStreamCreateWithFlags(&G.s[g], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&G.join[g], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      release_groups(G);
+      return FFS_E_DEVICE;
+    }
+    G.ready = true;
+  }
+  *out = &G;
+  return FFS_OK;
+}
+
 // A screened generation's surrogate inputs (ffs_surrogate.h).
 struct Screen {
   const float *table, *theta;
@@ -2907,6 +2993,80 @@ struct Screen {
   float *scores;
   int32_t *choice;
 };
+
+bool migrates(const ffs_ga_params &p, int gen) {
+  return p.mig_interval > 0 && p.mig_k > 0 && p.islands > 1 && gen % p.mig_interval == 0;
+}
+
+// Ring migration after the generation written to buffer 1 - cur.
+bool migrate(const ffs_ga_params &p, const GaLayout &L, int cur, int n, hipStream_t stream) {
+  const int K = p.rows * p.cols;
+  return launch(-1, migrate_collect_kernel, dim3(p.islands), dim3(256), (size_t)K, stream,
+                (const int32_t *)L.prio[1 - cur], (const int64_t *)L.obj[1 - cur], L.stage_prio,
+                L.stage_obj, K, n, p.mig_k) == hipSuccess &&
+         launch(-1, migrate_apply_kernel, dim3(p.islands), dim3(256), (size_t)K, stream,
+                L.prio[1 - cur], L.obj[1 - cur], L.elite, L.elite_obj,
+                (const int32_t *)L.stage_prio, (const int64_t *)L.stage_obj, K, n, p.mig_k,
+                p.islands) == hipSuccess;
+}
+
+// ga_step of the hybrid GA over G > 1 island groups (GroupStreams): group g
+// holds islands [islands * g / G, islands * (g + 1) / G).
+template <int MAXM>
+int ga_step_groups(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, int32_t n_gen,
+                   hipStream_t stream, int G, size_t shmem) {
+  std::lock_guard<std::mutex> lk(g_group_mu);
+  GroupStreams *GS = nullptr;
+  int rc = group_streams(&GS);
+  if (rc) return rc;
+  const ffs_ga_params &p = ga->params;
+  const DInst d = make_dinst(in, L.pq);
+  const int K = p.rows * p.cols, n = ga->n_genes, cap = ga->lds_slots;
+  const bool xy = p.encoding == 1;
+  const XyTab T{L.xyop, L.xyg0, in->n_ops};
+  bool ok = true, forked = false;
+  auto join = [&]() {
+    for (int g = 1; g < G; ++g)
+      ok = hipEventRecord(GS->join[g], GS->s[g]) == hipSuccess &&
+           hipStreamWaitEvent(stream, GS->join[g], 0) == hipSuccess && ok;
+    forked = false;
+  };
+  for (int32_t k = 0; ok && k < n_gen; ++k) {
+    const int gen = ga->generation + 1, cur = ga->cur;
+    if (!forked) {
+      forked = true;
+      ok = hipEventRecord(GS->fork, stream) == hipSuccess;
+      for (int g = 1; ok && g < G; ++g)
+        ok = hipStreamWaitEvent(GS->s[g], GS->fork, 0) == hipSuccess;
+    }
+    for (int g = 0; ok && g < G; ++g) {
+      const hipStream_t sg = g ? GS->s[g] : stream;
+      const int i0 = (int)((int64_t)p.islands * g / G);
+      const int i1 = (int)((int64_t)p.islands * (g + 1) / G);
+      GaDev A = make_gadev(ga, L, cur);
+      A.isl0 = i0;
+      A.islands = i1 - i0;
+      const dim3 grid((unsigned)((i1 - i0) * K));
+      const hipError_t e =
+          xy ? launch(1, ga_generation_xy_kernel, grid, dim3(kWave), shmem, sg, d, T, A, gen, cap)
+             : launch(1, ga_generation_kernel<MAXM>, grid, dim3(kWave), shmem, sg, d, A, gen, cap);
+      ok = e == hipSuccess &&
+           launch(2, replace_wave_kernel, dim3(i1 - i0), dim3(kWave), 0, sg,
+                  L.prio[1 - cur] + (size_t)i0 * K * n, L.obj[1 - cur] + (size_t)i0 * K,
+                  L.elite + (size_t)i0 * n, L.elite_obj + i0, K, n) == hipSuccess;
+    }
+    if (ok && migrates(p, gen)) {
+      join();
+      ok = ok && migrate(p, L, cur, n, stream);
+    }
+    if (ok) {
+      ga->cur = 1 - cur;
+      ga->generation = gen;
+    }
+  }
+  if (forked) join();
+  return ok ? FFS_OK : FFS_E_DEVICE;
+}
 
 template <int MAXM>
 int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t stream,
@@ -2919,6 +3079,18 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
   const XyTab T{L.xyop, L.xyg0, in->n_ops};
   const size_t shmem = xy ? lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap)
                           : lds_bytes(in->n_active, cap);
+  // Island groups for the hybrid GA whose overflowed decodes are redone by their
+  // own waves (the overflow kernel's list belongs to the whole population).
+  if (ga->params.scheme == FFS_GA_HYBRID && !scr && (cap >= in->horizon || L.inline_redo)) {
+    const int want = g_island_groups.load();
+    int G = want > 0 ? want : kMaxGroups;
+    if (G > ga->params.islands) G = ga->params.islands;
+    if (G > 1) {
+      ga->island_groups = G;
+      return ga_step_groups<MAXM>(ga, in, L, n_gen, stream, G, shmem);
+    }
+  }
+  ga->island_groups = 1;
   for (int32_t k = 0; k < n_gen; ++k) {
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
@@ -2961,18 +3133,8 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     if (launch(2, replace_wave_kernel, dim3(ga->params.islands), dim3(kWave), 0, stream,
                L.prio[1 - cur], L.obj[1 - cur], L.elite, L.elite_obj, K, n) != hipSuccess)
       return FFS_E_DEVICE;
-    const ffs_ga_params &p = ga->params;
-    if (p.mig_interval > 0 && p.mig_k > 0 && p.islands > 1 && gen % p.mig_interval == 0) {
-      if (launch(-1, migrate_collect_kernel, dim3(p.islands), dim3(256), (size_t)K, stream,
-                 (const int32_t *)L.prio[1 - cur], (const int64_t *)L.obj[1 - cur], L.stage_prio,
-                 L.stage_obj, K, n, p.mig_k) != hipSuccess)
-        return FFS_E_DEVICE;
-      if (launch(-1, migrate_apply_kernel, dim3(p.islands), dim3(256), (size_t)K, stream,
-                 L.prio[1 - cur], L.obj[1 - cur], L.elite, L.elite_obj,
-                 (const int32_t *)L.stage_prio, (const int64_t *)L.stage_obj, K, n, p.mig_k,
-                 p.islands) != hipSuccess)
-        return FFS_E_DEVICE;
-    }
+    if (migrates(ga->params, gen) && !migrate(ga->params, L, cur, n, stream))
+      return FFS_E_DEVICE;
     ga->cur = 1 - cur;
     ga->generation = gen;
   }
@@ -3231,7 +3393,6 @@ int decode_job_vectors(const ffs_instance *inst, const int32_t *prio, int32_t po
 // Address of this GPU's copy of the no-allocation decode's scratch buffer,
 // looked up once per device (each GPU holds the array at its own address; the
 // array's name in host code is only a stand-in for the symbol).
-constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices] = {};
 
@@ -3448,6 +3609,7 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   ga->event = event;
   ga->generation = 0;
   ga->cur = 0;
+  ga->island_groups = 0;
   ga->workspace = workspace;
   ga->workspace_bytes = workspace_bytes;
   ga->lds_slots = cap;
@@ -3497,11 +3659,20 @@ int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *s
     return FFS_OK;
   }
   hipStream_t s = (hipStream_t)stream;
+  const int span = span_begin(s);
   switch (omp_of(inst->o_max)) {
-    case 4: return ga_step_impl<4>(ga, inst, n_generations, s);
-    case 8: return ga_step_impl<8>(ga, inst, n_generations, s);
-    default: return ga_step_impl<16>(ga, inst, n_generations, s);
+    case 4: rc = ga_step_impl<4>(ga, inst, n_generations, s); break;
+    case 8: rc = ga_step_impl<8>(ga, inst, n_generations, s); break;
+    default: rc = ga_step_impl<16>(ga, inst, n_generations, s);
   }
+  span_end(span, s, rc == FFS_OK ? n_generations : 0);
+  return rc;
+}
+
+int ga_set_island_groups(int32_t groups) {
+  if (groups < 0 || groups > kMaxGroups) return FFS_E_INVAL;
+  g_island_groups.store(groups);
+  return FFS_OK;
 }
 
 int sg_score(const ffs_surrogate *model, const float *table, int32_t n_genes, const int32_t *prio,

@@ -30,6 +30,7 @@ FFS_GA_HYBRID, FFS_GA_CLASSICAL, FFS_GA_CELLULAR = 0, 1, 2
 
 TIMING_DECODE, TIMING_GENERATION, TIMING_REPLACE, TIMING_OVERFLOW = 0, 1, 2, 3
 TIMING_BATCH, TIMING_SCREENED = 4, 5
+TIMING_STEP = 6  # whole ga_step calls, counted in generations
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
@@ -74,6 +75,7 @@ class FfsGa(ctypes.Structure):
         ("lds_slots", ctypes.c_int32), ("n_jobs", ctypes.c_int32), ("horizon", ctypes.c_int32),
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("prio", _vp * 2), ("obj", _vp * 2), ("elite", _vp), ("elite_obj", _vp),
+        ("island_groups", ctypes.c_int32),
     ]
 
 
@@ -98,6 +100,7 @@ _lib.ffs_ga_workspace_size.restype = ctypes.c_size_t
 _lib.ga_init.argtypes = [_P(FfsGa), _P(FfsInstance), _P(FfsGaParams), ctypes.c_uint64,
                          ctypes.c_uint64, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
 _lib.ga_step.argtypes = [_P(FfsGa), _P(FfsInstance), ctypes.c_int32, _vp]
+_lib.ga_set_island_groups.argtypes = [ctypes.c_int32]
 _lib.ga_best.argtypes = [_P(FfsGa), _vp, _vp, _vp]
 _lib.ga_view.argtypes = [_P(FfsGa), _P(FfsGaView)]
 _lib.ffs_reschedule_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -112,7 +115,8 @@ _lib.ffs_strerror.argtypes = [ctypes.c_int]
 _lib.ffs_strerror.restype = ctypes.c_char_p
 _lib.ffs_build_id.argtypes = []
 _lib.ffs_build_id.restype = ctypes.c_char_p
-for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_noalloc", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step", "ga_best", "ga_view",
+for _f in ("ffs_prepare", "ffs_decode", "ffs_decode_noalloc", "ffs_decode_xy", "ffs_status", "ga_init", "ga_step",
+           "ga_set_island_groups", "ga_best", "ga_view",
            "reschedule", "reschedule_static", "ffs_timing_enable", "ffs_timing_every",
            "ffs_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -444,6 +448,12 @@ def timing_enable(on=True, families=None, every=1):
     _check(_lib.ffs_timing_enable(mask), "ffs_timing_enable")
 
 
+def set_island_groups(groups):
+    """ga_set_island_groups: island groups ga_step runs on streams of their own
+    (0: the library's default of 4; 1: one stream)."""
+    _check(_lib.ga_set_island_groups(int(groups)), "ga_set_island_groups")
+
+
 def timing_read(family):
     ms = ctypes.c_double()
     n = ctypes.c_int64()
@@ -457,7 +467,8 @@ def exported_symbols():
     for name in ("ffs_prepare", "ffs_decode_workspace_size", "ffs_decode", "ffs_decode_noalloc",
                  "ffs_decode_xy",
                  "ffs_status",
-                 "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_best", "ga_view",
+                 "ffs_ga_workspace_size", "ga_init", "ga_step", "ga_set_island_groups", "ga_best",
+                 "ga_view",
                  "ffs_reschedule_workspace_size", "reschedule", "reschedule_static",
                  "ffs_timing_enable",
                  "ffs_timing_every", "ffs_timing_read", "ffs_strerror", "ffs_build_id", "ffs_batch_workspace_size",

@@ -28,6 +28,7 @@ class EventResult:
     lds_slots: int = 0             # on-chip profile slots the event's generations used
     decodes: int = 0               # the GA's decodes plus the executed plan's
     overflows: int = 0             # the GA's decodes redone off chip
+    island_groups: int = 1         # island groups the event's ga_step ran concurrently
 
 
 @dataclass
@@ -82,7 +83,8 @@ class EventLoop:
                          mach_out=self.plan_m[:n])
         ev = EventResult(e, int(d.s.rs), d.n_active, best_prio=prio, best_obj=obj,
                          work=ga.view()["work"].clone(), lds_slots=int(ga.ga.lds_slots),
-                         decodes=(1 + self.gens) * ga.ga.pop + 1, overflows=ga.overflows())
+                         decodes=(1 + self.gens) * ga.ga.pop + 1, overflows=ga.overflows(),
+                         island_groups=int(ga.ga.island_groups))
         if self.keep_instances:
             ev.instance = d
         if e + 1 < self.n_events:

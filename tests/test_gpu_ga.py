@@ -3,6 +3,8 @@
 The Philox stream makes every generation recomputable from its predecessor,
 so GPU and oracle populations, objectives and elites must agree bit for bit.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -166,6 +168,43 @@ def test_ga_is_deterministic():
         ga.step(25)
         runs.append(_state(ga))
     _same(runs[0], runs[1], "determinism")
+
+
+def test_ga_island_groups_change_nothing():
+    """ga_step over 1, 3 and 4 concurrent island groups gives the same populations,
+    objectives and elites, for job vectors and X/Y chromosomes. Config 2 has 32
+    islands: groups of 10-11 and of 8; the migrations at generations 10 and 20
+    join the groups in mid-call and calls of 7 and 18 generations fork and join at
+    their ends. The generation launches counted with HIP events show that the
+    grouped runs did launch one generation kernel per group."""
+    torch, ffsga = _ffs()
+    wl = W.config2(3)
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    try:
+        for enc in (0, 1):
+            gp = dataclasses.replace(wl.ga, encoding=enc)
+            runs = {}
+            for groups in (1, 3, 4):
+                _say("island groups", groups, "encoding", enc)
+                ffsga.set_island_groups(groups)
+                ga = ffsga.GA(d, ffsga.GaConfig.of(gp), wl.seed, wl.shop, 0)
+                ffsga.timing_enable(True, families=[ffsga.TIMING_GENERATION], every=1)
+                ga.step(7)
+                ga.step(18)
+                torch.cuda.synchronize()
+                _, launches = ffsga.timing_read(ffsga.TIMING_GENERATION)
+                ffsga.timing_enable(False)
+                assert launches == 25 * groups, (groups, launches)
+                ga.status()
+                runs[groups] = _state(ga)
+            for groups in (3, 4):
+                _same(runs[groups], runs[1], f"{groups} island groups, encoding {enc}")
+    finally:
+        ffsga.timing_enable(False)
+        ffsga.set_island_groups(0)
+    for bad in (-1, 5):
+        with pytest.raises(ffsga.FfsError):
+            ffsga.set_island_groups(bad)
 
 
 def test_ga_auto_sized_profile_changes_nothing():
