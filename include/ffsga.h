@@ -283,22 +283,26 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
 int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *stream);
 
 /* How many island groups ga_step runs concurrently (process-wide; 0, the
- * default, means 4; 1 runs every launch on the caller's stream). Between two
+ * default, means 4; 1 runs every launch on the caller's stream); unless
+ * groups is 1, also creates the current device's group streams now. Between two
  * migrations the islands of the hybrid GA (Section 4.4) share nothing, so
  * ga_step splits them into `groups` contiguous groups (group g: islands
  * [islands * g / groups, islands * (g + 1) / groups)) and runs each group's
  * generations on a stream of its own: a group that has decoded and replaced
  * its islands starts its next generation while others still decode. The
  * library creates the extra streams (default priority) and events once per
- * device; they fork from the caller's stream, and ga_step joins them back into
- * it before every migration and before it returns, so the caller's stream
- * orders everything as before. Results are the same for every grouping (draws
- * are keyed by the global slot). Grouping applies to the hybrid scheme whose
- * overflowed decodes are redone by their own waves (see ga_step), not to
- * ga_step_screened or the comparison GAs, and never to more groups than
- * islands. Calls of ga_step from several host threads take turns enqueueing
- * on one device while grouping is in use.
- * Errors: FFS_E_INVAL (groups < 0 or > 4). */
+ * device, here or at the first grouped ga_step; they fork from the caller's
+ * stream, and ga_step joins them back into it before every migration and
+ * before it returns, so the caller's stream orders everything as before. The
+ * groups only overlap when their streams sit on hardware queues of their own:
+ * the runtime spreads streams over a few queues per process in the order they
+ * are created, so call this before creating other streams. Results are the
+ * same for every grouping (draws are keyed by the global slot). Grouping
+ * applies to the hybrid scheme whose overflowed decodes are redone by their
+ * own waves (see ga_step), not to ga_step_screened or the comparison GAs, and
+ * never to more groups than islands. Calls of ga_step from several host
+ * threads take turns enqueueing on one device while grouping is in use.
+ * Errors: FFS_E_INVAL (groups < 0 or > 4), FFS_E_DEVICE. */
 int ga_set_island_groups(int32_t groups);
 
 /* Copy the best elite (lowest island on ties) to prio_out (device

@@ -3672,7 +3672,10 @@ int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *s
 int ga_set_island_groups(int32_t groups) {
   if (groups < 0 || groups > kMaxGroups) return FFS_E_INVAL;
   g_island_groups.store(groups);
-  return FFS_OK;
+  if (groups == 1) return FFS_OK;
+  std::lock_guard<std::mutex> lk(g_group_mu);
+  GroupStreams *GS = nullptr;
+  return group_streams(&GS);
 }
 
 int sg_score(const ffs_surrogate *model, const float *table, int32_t n_genes, const int32_t *prio,

@@ -162,6 +162,7 @@ class DeviceInstance:
     def __init__(self, s: FfsInstance, tensors: dict):
         self.s = s
         self.t = tensors
+        _make_group_streams(tensors["proc"].device)
 
     @classmethod
     def from_host(cls, inst, device="cuda", prepare=True, workspace=None):
@@ -448,10 +449,32 @@ def timing_enable(on=True, families=None, every=1):
     _check(_lib.ffs_timing_enable(mask), "ffs_timing_enable")
 
 
+_island_groups = 0        # the value last given to ga_set_island_groups
+_group_stream_devices = set()
+
+
 def set_island_groups(groups):
     """ga_set_island_groups: island groups ga_step runs on streams of their own
-    (0: the library's default of 4; 1: one stream)."""
+    (0: the library's default of 4; 1: one stream). Also creates the current
+    device's group streams."""
+    global _island_groups
     _check(_lib.ga_set_island_groups(int(groups)), "ga_set_island_groups")
+    _island_groups = int(groups)
+    if _island_groups != 1:
+        _group_stream_devices.add(torch.cuda.current_device())
+
+
+def _make_group_streams(device):
+    """Create `device`'s island-group streams with the first instance placed on it:
+    before the streams of a Batch, so that they get hardware queues of their own."""
+    idx = torch.device(device).index
+    if idx is None:
+        idx = torch.cuda.current_device()
+    if _island_groups == 1 or idx in _group_stream_devices:
+        return
+    with torch.cuda.device(idx):
+        _check(_lib.ga_set_island_groups(_island_groups), "ga_set_island_groups")
+    _group_stream_devices.add(idx)
 
 
 def timing_read(family):
