@@ -183,17 +183,19 @@ def cpu_model():
 
 
 def profile_figures(kname, workload):
-    """HBM bytes per launch, VALU issue rate and VALU lane utilisation from the
+    """HBM bytes per decode, VALU issue rate and VALU lane utilisation from the
     rocprofv3 counter runs committed under profiles/, used only when they were
-    taken on this very build: (traffic, issue TOP/s, lane utilisation)."""
+    taken on this very build: (traffic per decode, issue TOP/s, lane utilisation).
+    The counter runs launch one wave per decode, so a launch's bytes over its
+    waves are the bytes of one decode."""
     from paper_1903_10741_amd import ffsga
     tpath = os.path.join(ROOT, "profiles", f"{kname}_{workload}.traffic.json")
     if not os.path.exists(tpath):
         return None, None, None
     t = json.load(open(tpath))
-    if t.get("build_id") != ffsga.ffs_build_id():
+    if t.get("build_id") != ffsga.ffs_build_id() or not t.get("decodes_per_launch"):
         return None, None, None
-    return (t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"],
+    return ((t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]) / t["decodes_per_launch"],
             t.get("valu_issue_tlops"), t.get("valu_lane_utilisation"))
 
 
@@ -267,6 +269,8 @@ def bench_large(args):
     else:
         achieved = work_per_decode * wl.ga.pop / avg_launch_s / 1e12
     traffic, valu_issue, lane_util = profile_figures("ga_generation_kernel", "large-200x10x4-6")
+    if traffic is not None:
+        traffic *= wl.ga.pop // groups  # HBM bytes per launch
     best = {}
     for ev in events:
         best.setdefault(ev.event, int(ev.best_obj.item()))
@@ -972,6 +976,8 @@ def bench_paper(args, steps, warmup):
 
     kname = "ga_generation_xy_kernel" if xy else "ga_generation_kernel"
     traffic, valu_issue, lane_util = profile_figures(kname, "paper-50x5x3")
+    if traffic is not None:
+        traffic *= wl.ga.pop // groups  # HBM bytes per launch
     avg_launch_s = gen_ms / 1e3 / max(gen_launches, 1)
     per_gen_s = step_ms / 1e3 / max(step_gens, 1)
     # One launch decodes pop / groups chromosomes. With one group the launch's
