@@ -122,7 +122,8 @@ int sg_train_step(ffs_surrogate *model, const float *feats, int32_t n_genes, con
  * block v; candidate 0 is the plain generation's child), scores them with
  * `table` (from sg_score_table on this instance and model), keeps the lowest
  * score (ties to the lowest v) and decodes it exactly; replacement and
- * migration follow as in ga_step. scores (device float32 [variants][pop])
+ * migration follow as in ga_step, in island groups as ga_step's
+ * (ga_set_island_groups). scores (device float32 [variants][pop])
  * and choice (device int32 [pop]), each may be NULL, receive the last
  * generation's candidate scores and kept candidates.
  * Errors: as ga_step, and FFS_E_INVAL for variants outside 1..FFS_SG_MAX_VARIANTS. */

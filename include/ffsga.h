@@ -299,8 +299,8 @@ int ga_step(ffs_ga *ga, const ffs_instance *inst, int32_t n_generations, void *s
  * are created, so call this before creating other streams. Results are the
  * same for every grouping (draws are keyed by the global slot). Grouping
  * applies to the hybrid scheme whose overflowed decodes are redone by their
- * own waves (see ga_step), not to ga_step_screened or the comparison GAs, and
- * never to more groups than islands. Calls of ga_step from several host
+ * own waves (see ga_step), ga_step_screened's included, not to the comparison
+ * GAs, and never to more groups than islands. Calls of ga_step from several host
  * threads take turns enqueueing on one device while grouping is in use.
  * Errors: FFS_E_INVAL (groups < 0 or > 4), FFS_E_DEVICE. */
 int ga_set_island_groups(int32_t groups);

@@ -1767,10 +1767,11 @@ __global__ __launch_bounds__(64) void sg_score_kernel(const float *table, const 
 template <int MAXM>
 __global__ __launch_bounds__(64) void ga_screened_kernel(DInst I, GaDev A, int gen, int cap,
                                                          const float *table, const float *theta,
-                                                         int V, float *scores, int32_t *choice) {
+                                                         int V, float *scores, int32_t *choice,
+                                                         int pop) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int K = A.rows * A.cols, pop = K * A.islands;
-  const int i = slot_of_block(blockIdx.x, K, A.islands);
+  const int K = A.rows * A.cols;
+  const int i = A.isl0 * K + slot_of_block(blockIdx.x, K, A.islands);
   const Lds l = carve_lds(smem, I.n);
   const float b3 = theta[FFS_SG_PARAMS - 1];
   int best = 0;
@@ -3014,7 +3015,7 @@ bool migrate(const ffs_ga_params &p, const GaLayout &L, int cur, int n, hipStrea
 // holds islands [islands * g / G, islands * (g + 1) / G).
 template <int MAXM>
 int ga_step_groups(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, int32_t n_gen,
-                   hipStream_t stream, int G, size_t shmem) {
+                   hipStream_t stream, int G, size_t shmem, const Screen *scr) {
   std::lock_guard<std::mutex> lk(g_group_mu);
   GroupStreams *GS = nullptr;
   int rc = group_streams(&GS);
@@ -3048,8 +3049,10 @@ int ga_step_groups(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, int32_
       A.islands = i1 - i0;
       const dim3 grid((unsigned)((i1 - i0) * K));
       const hipError_t e =
-          xy ? launch(1, ga_generation_xy_kernel, grid, dim3(kWave), shmem, sg, d, T, A, gen, cap)
-             : launch(1, ga_generation_kernel<MAXM>, grid, dim3(kWave), shmem, sg, d, A, gen, cap);
+          scr ? launch(5, ga_screened_kernel<MAXM>, grid, dim3(kWave), shmem, sg, d, A, gen, cap,
+                       scr->table, scr->theta, scr->variants, scr->scores, scr->choice, ga->pop)
+          : xy ? launch(1, ga_generation_xy_kernel, grid, dim3(kWave), shmem, sg, d, T, A, gen, cap)
+               : launch(1, ga_generation_kernel<MAXM>, grid, dim3(kWave), shmem, sg, d, A, gen, cap);
       ok = e == hipSuccess &&
            launch(2, replace_wave_kernel, dim3(i1 - i0), dim3(kWave), 0, sg,
                   L.prio[1 - cur] + (size_t)i0 * K * n, L.obj[1 - cur] + (size_t)i0 * K,
@@ -3081,13 +3084,13 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
                           : lds_bytes(in->n_active, cap);
   // Island groups for the hybrid GA whose overflowed decodes are redone by their
   // own waves (the overflow kernel's list belongs to the whole population).
-  if (ga->params.scheme == FFS_GA_HYBRID && !scr && (cap >= in->horizon || L.inline_redo)) {
+  if (ga->params.scheme == FFS_GA_HYBRID && (cap >= in->horizon || L.inline_redo)) {
     const int want = g_island_groups.load();
     int G = want > 0 ? want : kMaxGroups;
     if (G > ga->params.islands) G = ga->params.islands;
     if (G > 1) {
       ga->island_groups = G;
-      return ga_step_groups<MAXM>(ga, in, L, n_gen, stream, G, shmem);
+      return ga_step_groups<MAXM>(ga, in, L, n_gen, stream, G, shmem, scr);
     }
   }
   ga->island_groups = 1;
@@ -3108,7 +3111,7 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
                  gen, cap);
     } else if (scr)
       e = launch(5, ga_screened_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen, cap,
-                 scr->table, scr->theta, scr->variants, scr->scores, scr->choice);
+                 scr->table, scr->theta, scr->variants, scr->scores, scr->choice, pop);
     else if (xy)
       e = launch(1, ga_generation_xy_kernel, dim3(pop), dim3(kWave), shmem, stream, d, T, A, gen,
                  cap);
