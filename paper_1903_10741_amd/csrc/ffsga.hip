@@ -128,7 +128,8 @@ __device__ __forceinline__ u64 ballot64(bool p) { return __builtin_amdgcn_ballot
 // Instance as the kernels see it.
 // ---------------------------------------------------------------------------
 struct DInst {
-  const uint32_t *pq;        // [n_jobs][g][omp]: P | Q << 16
+  const uint32_t *pq;        // [n][g][omp]: P | Q << 16 of the active jobs, in gene order
+  const int32_t *due_k;      // [n]: due dates of the active jobs, in gene order
   const int32_t *nm;         // [g]
   const int32_t *due;        // [n_jobs]
   const int32_t *first;      // [n_jobs]
@@ -293,9 +294,11 @@ __device__ __forceinline__ void GlobalProfile::commit(int t, int p, int q) const
 enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 
 // LDS of one wave (one chromosome of n genes; words of a packed P|Q row per op):
-//   jobs  [n+1]      by rank: job | first_stage << 24  (correction scratch before decode)
-//   rdy   [n+1]      by rank: completion of the job's last placed stage (scratch before);
-//                    an op's end replaces it as soon as the op is placed
+//   rdy   [n+1]      by rank: completion of the job's last placed stage, slots after RS
+//                    (scratch before the decode); an op's end replaces it as soon as the
+//                    op is placed
+//   jobs  [n+2]      by rank: 16-bit gene index | min(first_stage, 15) << 12
+//                    (correction scratch before the decode)
 //   op    [n+2]      the current stage's ops in order, as 16-bit ranks (two spare
 //                    records that the op loop prefetches past the last)
 //   rec   [kRing]    packed P | Q << 16 rows of the stage's ops, one word per machine,
@@ -306,8 +309,8 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //                    at least n words): it is dead once the decode has built the ranks,
 //                    before the profile is cleared
 struct Lds {
-  int32_t *gene, *jobs, *rdy;
-  uint16_t *op;
+  int32_t *gene, *rdy;
+  uint16_t *jobs, *op;
   uint32_t *rec;
   uint8_t *prof;
 };
@@ -319,7 +322,7 @@ constexpr int kRing = kWave + 16;
 // LDS bytes before the profile region, and in all (cap = 0: no on-chip profile,
 // the region still holds the genes).
 __host__ __device__ inline size_t lds_head(int n) {
-  return 2 * align_up((size_t)4 * n + 4, 16) + align_up((size_t)2 * n + 4, 16) + 4 * kRing;
+  return align_up((size_t)4 * n + 4, 16) + 2 * align_up((size_t)2 * n + 4, 16) + 4 * kRing;
 }
 __host__ __device__ inline size_t lds_bytes(int n, int cap) {
   const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0, gene = align_up((size_t)4 * n, 16);
@@ -328,11 +331,11 @@ __host__ __device__ inline size_t lds_bytes(int n, int cap) {
 
 __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   Lds l;
-  const size_t a = align_up((size_t)4 * n + 4, 16);
-  l.jobs = (int32_t *)smem;
-  l.rdy = (int32_t *)(smem + a);
-  l.op = (uint16_t *)(smem + 2 * a);
-  l.rec = (uint32_t *)(smem + 2 * a + align_up((size_t)2 * n + 4, 16));
+  const size_t a = align_up((size_t)4 * n + 4, 16), b = align_up((size_t)2 * n + 4, 16);
+  l.rdy = (int32_t *)smem;
+  l.jobs = (uint16_t *)(smem + a);
+  l.op = (uint16_t *)(smem + a + b);
+  l.rec = (uint32_t *)(smem + a + 2 * b);
   l.prof = (uint8_t *)l.rec + 4 * kRing;
   l.gene = (int32_t *)l.prof;
   return l;
@@ -377,6 +380,16 @@ __device__ __forceinline__ int wave_max32(int v) {
   return v;
 }
 
+// Whether the job of packed rank record jk has an op at stage s: its first
+// unfrozen stage is at most s. The record holds min(first stage, 15), exact
+// unless the stage is 15 or later with more than 16 stages (`exact`, uniform:
+// then a record of 15 is looked up).
+__device__ __forceinline__ bool live_at(const DInst &I, uint32_t jk, int s, bool exact) {
+  bool live = (int)(jk >> 12) <= s;
+  if (exact && (jk >> 12) == 15) live = ld_const(I.first, ld_const(I.active, jk & 0xFFF)) <= s;
+  return live;
+}
+
 // Decode the chromosome in l.gene (Section 4.3, Algorithm 2, eq. (1)) with the
 // power profile `prof`. On kDecOk lane 0 has written *obj_out. Every lane
 // calls this; the result is uniform.
@@ -399,24 +412,27 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   const int lane = __lane_id();
   const int n = I.n;
   const u64 below = (1ull << lane) - 1;
-  // Rank of gene k: n - prio_k (larger priority first).
-  for (int x = lane; x < n; x += kWave) l.jobs[x] = -1;
+  // Rank of gene k: n - prio_k (larger priority first). Times from here on
+  // count slots after RS (a job ready before RS has a negative ready time).
+  const int rs = I.rs;
+  for (int x = lane; x < n; x += kWave) l.jobs[x] = 0xFFFF;
   int bad = 0;
   __asm__ volatile("" ::: "memory");
   for (int k = lane; k < n; k += kWave) {
     const int v = l.gene[k];
-    if (v >= 1 && v <= n) l.jobs[n - v] = k;
+    if (v >= 1 && v <= n) l.jobs[n - v] = (uint16_t)k;
     else bad = 1;
   }
   __asm__ volatile("" ::: "memory");
   for (int x = lane; x < n; x += kWave) {
     const int k = l.jobs[x];
-    if (k < 0) {
+    if (k == 0xFFFF) {
       bad = 1;
     } else {
       const int j = ld_const(I.active, k);
-      l.jobs[x] = j | (ld_const(I.first, j) << 24);
-      l.rdy[x] = ld_const(I.ready, j);
+      l.jobs[x] = (uint16_t)(k | min(ld_const(I.first, j), 15) << 12);
+      l.rdy[x] = ld_const(I.ready, j) - rs;  // may be negative: every use takes a max with
+                                             // a machine's free time, which is at least 0
     }
   }
   if (ballot64(bad)) return kDecInval;
@@ -438,13 +454,13 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   }
   prof.order();
 
-  const int rs = I.rs, cap = prof.cap;
+  const int cap = prof.cap;
   const bool power_ect = RULES && (I.rules & FFS_RULE_POWER_ECT) != 0;
   const bool fifo = RULES && (I.rules & FFS_RULE_FIFO) != 0;
   int64_t work = 0;
   for (int s = 0; s < I.g; ++s) {
     const int os = ld_const(I.nm, s);
-    int fr = lane < os ? ld_const(I.mfree, (size_t)s * I.om + lane) : kNoMachine;
+    int fr = lane < os ? max(ld_const(I.mfree, (size_t)s * I.om + lane) - rs, 0) : kNoMachine;
     // The stage's ops, compacted in decode order (by rank, i.e. priority, or
     // with FFS_RULE_FIFO by the completion of the previous stage, then rank),
     // plus a spare record so the op loop can prefetch one past the last.
@@ -454,17 +470,17 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     // job's place is the number of keys below its own, counted against keys
     // broadcast one lane at a time.
     const bool fifo_reg = fifo && n <= 2 * kWave;
+    const bool exact = I.g > 16 && s >= 15;
     u64 fk0 = ~0ull, fk1 = ~0ull;
     if (fifo_reg) {
-      if (lane < n && (l.jobs[lane] >> 24) <= s)
-        fk0 = (u64)(uint32_t)l.rdy[lane] << 32 | (uint32_t)lane;
-      if (kWave + lane < n && (l.jobs[kWave + lane] >> 24) <= s)
-        fk1 = (u64)(uint32_t)l.rdy[kWave + lane] << 32 | (uint32_t)(kWave + lane);
+      if (lane < n && live_at(I, l.jobs[lane], s, exact))
+        fk0 = (u64)(uint32_t)(l.rdy[lane] + rs) << 32 | (uint32_t)lane;
+      if (kWave + lane < n && live_at(I, l.jobs[kWave + lane], s, exact))
+        fk1 = (u64)(uint32_t)(l.rdy[kWave + lane] + rs) << 32 | (uint32_t)(kWave + lane);
     }
     for (int b = 0; b < n; b += kWave) {
       const int x = b + lane;
-      const int jf = x < n ? l.jobs[x] : (127 << 24);
-      const bool live = x < n && (jf >> 24) <= s;
+      const bool live = x < n && live_at(I, l.jobs[x], s, exact);
       const u64 mk = ballot64(live);
       if (live) {
         int k = cnt + __popcll(mk & below);
@@ -480,7 +496,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
           k = 0;
           for (int y = 0; y < n; ++y) {
             const int cy = l.rdy[y];
-            k += (l.jobs[y] >> 24) <= s && (cy < cx || (cy == cx && y < x));
+            k += live_at(I, l.jobs[y], s, exact) && (cy < cx || (cy == cx && y < x));
           }
         }
         l.op[k] = (uint16_t)x;
@@ -500,8 +516,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     const size_t pq_job = (size_t)I.g * I.omp;
     auto row_word = [&](int k) -> uint32_t {
       if (lk >= C || k >= cnt) return 0u;
-      const int j = l.jobs[l.op[k]] & 0xFFFFFF;
-      return pq_stage[(size_t)j * pq_job];
+      return pq_stage[(size_t)(l.jobs[l.op[k]] & 0xFFF) * pq_job];
     };
     {
       const uint32_t w0 = row_word(lk);
@@ -552,9 +567,8 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       // the previous op's profile words, formed while this op's keys reduce
       const uint32_t cword = commit_word(ct, cp, cq);
       // Machine of earliest completion (ties to the lowest index).
-      const int mx = max(max(ex, rs), fr);
-      const int t0v = mx - rs;  // earliest start on this lane's machine, slots after RS
-      const uint32_t key = ((uint32_t)(mx + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
+      const int t0v = max(ex, fr);  // earliest start on this lane's machine
+      const uint32_t key = ((uint32_t)(t0v + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
       uint32_t kmin = machine_min_scalar<MAXM>(key);
       int t = 0;
       StageWork cw = 0;
@@ -566,7 +580,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         // machine of least key goes first, then in index order only machines whose
         // key is below the best so far. Work: 3 per machine, plus the examined
         // slots and p of every machine pushed right.
-        const int ox = uni(max(ex, rs));  // uniform: keeps this loop on the scalar unit
+        const int ox = uni(ex);  // uniform: keeps this loop on the scalar unit
         const int first = (int)(kmin & 15u);
         uint32_t best = 0xFFFFFFFFu;
         cw = 3 * os;
@@ -576,10 +590,10 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
           if ((uint32_t)__builtin_amdgcn_readlane((int)key, m) >= best) continue;
           const uint32_t pqm = (uint32_t)__builtin_amdgcn_readlane((int)pqv, m);
           const int pm = (int)(pqm & 0xFFFFu);
-          const int t0m = max(ox, __builtin_amdgcn_readlane(fr, m)) - rs;
+          const int t0m = max(ox, __builtin_amdgcn_readlane(fr, m));
           const int tm = prof.place(t0m, pm, (uint32_t)(I.q_max - (int)(pqm >> 16)));
           cw += (StageWork)((tm - t0m) + pm);
-          const uint32_t km = ((uint32_t)(tm + pm + rs) << 4) | (uint32_t)m;
+          const uint32_t km = ((uint32_t)(tm + pm) << 4) | (uint32_t)m;
           if (km < best) {
             best = km;
             t = tm;
@@ -603,7 +617,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       ct = t;
       cp = p;
       cq = q;
-      const int end = t + p + rs;
+      const int end = t + p;
       fr = ffs_writelane(end, mb, fr);
       *rdy_at = PLAN ? end | (mb << 27) : end;
       stage_work = stage_work + cw;
@@ -617,7 +631,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     }
     prof.commit(ct, cp, cq);  // the stage's last op
     work += (int64_t)uniform_sum(stage_work) + (power_ect ? 0 : 3 * os * cnt);
-    if (wave_max32(lane < os ? fr : 0) - rs > cap) return kDecOverflow;
+    if (wave_max32(lane < os ? fr : 0) > cap) return kDecOverflow;
     __asm__ volatile("" ::: "memory");
     // With a plan: start and machine of every op, and the machine bits taken
     // out of the jobs' completion times.
@@ -626,10 +640,10 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
         const int x = l.op[k];
         const int e = l.rdy[x];
         const int end = e & (kMaxTime - 1), mb = e >> 27;
-        const size_t j = (size_t)(l.jobs[x] & 0xFFFFFF);
+        const size_t gk = l.jobs[x] & 0xFFF, j = (size_t)ld_const(I.active, gk);
         l.rdy[x] = end;
-        const uint32_t pqb = I.pq[(j * I.g + s) * I.omp + mb];
-        start_out[j * I.g + s] = end - (int)(pqb & 0xFFFFu);
+        const uint32_t pqb = I.pq[(gk * I.g + s) * I.omp + mb];
+        start_out[j * I.g + s] = end + rs - (int)(pqb & 0xFFFFu);
         mach_out[j * I.g + s] = mb;
       }
       __asm__ volatile("" ::: "memory");
@@ -639,14 +653,14 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   int64_t tard = 0;
   int cmax = 0;
   for (int x = lane; x < n; x += kWave) {
-    const int c = l.rdy[x];
-    const int late = c - ld_const(I.due, l.jobs[x] & 0xFFFFFF);
+    const int c = l.rdy[x] + rs;
+    const int late = c - ld_const(I.due_k, l.jobs[x] & 0xFFF);
     tard += late > 0 ? late : 0;
     cmax = max(cmax, c);
   }
   tard = wave_sum64(tard);
   cmax = wave_max32(cmax);
-  if (span_max && lane == 0) atomicMax(span_max, cmax - I.rs);  // profile slots this decode used
+  if (span_max && lane == 0) atomicMax(span_max, cmax - rs);  // profile slots this decode used
   cmax = max(cmax, I.frozen_cmax);
   if (lane == 0) {
     *obj_out = (int64_t)I.wt * (I.frozen_t + tard) + cmax;
@@ -794,8 +808,9 @@ __device__ __forceinline__ int select_winner(const GaDev &A, int i) {
 
 // Correction (Fig. 11): first occurrences stay; later duplicates take the
 // values missing from 1..n in ascending order, in scan order.
-// first_pos: LDS [n + 1], miss: LDS [n].
-__device__ void correct_lds(int32_t *gene, int n, int32_t *first_pos, int32_t *miss) {
+// first_pos: LDS [n + 1], miss: LDS [n] (16-bit words when n < 65536).
+template <class M>
+__device__ void correct_lds(int32_t *gene, int n, int32_t *first_pos, M *miss) {
   const int lane = __lane_id();
   for (int v = lane; v <= n; v += kWave) first_pos[v] = INT_MAX;
   __asm__ volatile("" ::: "memory");
@@ -810,7 +825,7 @@ __device__ void correct_lds(int32_t *gene, int n, int32_t *first_pos, int32_t *m
     const int v = b + lane + 1;
     const bool missing = v <= n && first_pos[v] == INT_MAX;
     const u64 m = ballot64(missing);
-    if (missing) miss[rank + __popcll(m & below)] = v;
+    if (missing) miss[rank + __popcll(m & below)] = (M)v;
     rank += __popcll(m);
   }
   __asm__ volatile("" ::: "memory");
@@ -846,8 +861,8 @@ __device__ void build_child(const GaDev &A, int n, int i, int gen, const Lds &l,
                             const int32_t *mine, const int32_t *other, int cross_idx,
                             int variant, bool store) {
   const int lane = __lane_id();
-  int32_t *first_pos = l.jobs;  // n + 1 words, then n words in rdy: free before the decode
-  int32_t *miss = l.rdy;
+  int32_t *first_pos = l.rdy;  // n + 1 words, then n halfwords in jobs: free before the decode
+  uint16_t *miss = l.jobs;
   u64 dw[4];
   {
     const bool xl = lane == 0;
@@ -1337,8 +1352,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     for (int i = 0; i < len; ++i) {
       const int kk = k + i, op = ld_const(T.op, kk), x = op & 0xFFFFF, s = op >> 20;
       const int m = l.gx[kk];
-      const int j = ld_const(I.active, x);
-      const uint32_t pq = ld_const(I.pq, ((size_t)j * I.g + s) * I.omp + m);
+      const uint32_t pq = ld_const(I.pq, ((size_t)x * I.g + s) * I.omp + m);
       l.zrec[pos + i] = make_int2(x | (s * I.om + m) << 12, (int)pq);
     }
     base += __builtin_amdgcn_readlane(incl, kWave - 1);
@@ -1454,7 +1468,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   int cmax = 0;
   for (int x = lane; x < n; x += kWave) {
     const int c = l.rdy[x];
-    const int late = c - ld_const(I.due, ld_const(I.active, x));
+    const int late = c - ld_const(I.due_k, x);
     tard += late > 0 ? late : 0;
     cmax = max(cmax, c);
   }
@@ -2180,21 +2194,26 @@ __global__ __launch_bounds__(64) void clear_header_kernel(Header *h) {
   ((int32_t *)h)[threadIdx.x] = 0;
 }
 
-__global__ void pack_kernel(const int32_t *proc, const int32_t *power, uint32_t *pq, int rows,
-                            int om, int omp) {
-  const size_t total = (size_t)rows * omp;
-  for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
-       x += (size_t)gridDim.x * blockDim.x) {
+// The decoders' per-instance table: row k * g + s holds stage s of active job
+// k (gene order) as P | Q << 16 per machine, omp words (zero past o_max); the
+// n words after the rows hold the active jobs' due dates.
+__global__ void pack_kernel(const int32_t *proc, const int32_t *power, const int32_t *due,
+                            const int32_t *active, uint32_t *pq, int n, int g, int om, int omp) {
+  const size_t total = (size_t)n * g * omp;
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += step) {
     const size_t row = x / omp;
     const int m = (int)(x % omp);
+    const size_t k = row / g, st = row % g;
     uint32_t v = 0;
     if (m < om) {
-      const uint32_t p = (uint32_t)proc[row * om + m] & 0xFFFFu;
-      const uint32_t q = (uint32_t)power[row * om + m] & 0xFFFFu;
-      v = p | (q << 16);
+      const size_t src = ((size_t)active[k] * g + st) * om + m;
+      v = ((uint32_t)proc[src] & 0xFFFFu) | (((uint32_t)power[src] & 0xFFFFu) << 16);
     }
     pq[x] = v;
   }
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)n; k += step)
+    pq[total + k] = (uint32_t)due[active[k]];
 }
 
 struct PrepArgs {
@@ -2567,9 +2586,12 @@ int check_host(const ffs_instance *in) {
   return FFS_OK;
 }
 
-DInst make_dinst(const ffs_instance *in, const uint32_t *pq) {
+// pq: the table pack_kernel wrote at row width omp (0: omp_of(o_max)).
+DInst make_dinst(const ffs_instance *in, const uint32_t *pq, int omp = 0) {
   DInst d;
+  if (omp == 0) omp = omp_of(in->o_max);
   d.pq = pq;
+  d.due_k = (const int32_t *)(pq + (size_t)in->n_active * in->n_stages * omp);
   d.nm = in->n_machines;
   d.due = in->due;
   d.first = in->first_stage;
@@ -2581,7 +2603,7 @@ DInst make_dinst(const ffs_instance *in, const uint32_t *pq) {
   d.n_jobs = in->n_jobs;
   d.g = in->n_stages;
   d.om = in->o_max;
-  d.omp = omp_of(in->o_max);
+  d.omp = omp;
   d.q_max = in->q_max;
   d.wt = in->wt;
   d.rs = in->rs;
@@ -2603,8 +2625,12 @@ int resolve_cap(const ffs_instance *in, int32_t lds_slots) {
   return cap;
 }
 
+// Bytes of pack_kernel's table: n x g rows of omp words, then n due dates.
+size_t pq_bytes(int n, int g, int omp) {
+  return align_up((size_t)n * g * omp * 4 + (size_t)n * 4 + 64, 256);
+}
 size_t pq_bytes(const ffs_instance *in) {
-  return align_up((size_t)in->n_jobs * in->n_stages * omp_of(in->o_max) * 4 + 64, 256);
+  return pq_bytes(in->n_active, in->n_stages, omp_of(in->o_max));
 }
 
 struct DecodeLayout {
@@ -2679,13 +2705,14 @@ int run_decode_xy(const ffs_instance *in, const int32_t *genes, int32_t pop, int
 
 int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t stream);
 
-int pack(const ffs_instance *in, uint32_t *pq, hipStream_t stream) {
-  const int rows = in->n_jobs * in->n_stages;
-  if (rows == 0) return FFS_OK;
-  const int omp = omp_of(in->o_max);
-  const int blocks = (int)((rows * (size_t)omp + 255) / 256);
+int pack(const ffs_instance *in, uint32_t *pq, hipStream_t stream, int omp = 0) {
+  if (in->n_active == 0) return FFS_OK;
+  if (omp == 0) omp = omp_of(in->o_max);
+  const size_t words = (size_t)in->n_active * in->n_stages * omp;
+  const int blocks = (int)((words + 255) / 256);
   hipError_t e = launch(-1, pack_kernel, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, stream,
-                        in->proc, in->power, pq, rows, in->o_max, omp);
+                        in->proc, in->power, in->due, in->active, pq, in->n_active,
+                        in->n_stages, in->o_max, omp);
   return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
 }
 
@@ -3209,7 +3236,7 @@ BatchLayout batch_layout(void *ws, const ffs_batch_params *p) {
   // one slot's region
   size_t so = 0;
   L.off_pq = so;
-  so += align_up((size_t)p->max_jobs * p->max_stages * omp_of(p->o_max) * 4 + 64, 256);
+  so += pq_bytes(p->max_genes, p->max_stages, omp_of(p->o_max));
   for (int k = 0; k < 2; ++k) {
     L.off_prio[k] = so;
     so += align_up(pop * n * 4 + 4, 256);
@@ -3808,18 +3835,10 @@ int ga_batch_set(ffs_batch *b, int32_t slot, const ffs_instance *inst, uint64_t 
   BatchLayout L = batch_layout(b->workspace, &p);
   uint8_t *base = L.slot_base + L.slot_stride * slot;
   // pack the instance's rows at the batch's row width
-  ffs_instance packed_view = *inst;
-  const int rows = inst->n_jobs * inst->n_stages;
-  if (rows > 0) {
-    const int blocks = (int)((rows * (size_t)b->omp + 255) / 256);
-    if (launch(-1, pack_kernel, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, inst->proc,
-               inst->power, (uint32_t *)(base + L.off_pq), rows, inst->o_max, b->omp) != hipSuccess)
-      return FFS_E_DEVICE;
-  }
+  if ((rc = pack(inst, (uint32_t *)(base + L.off_pq), s, b->omp))) return rc;
   BatchSlot S;
   memset(&S, 0, sizeof(S));
-  S.I = make_dinst(&packed_view, (const uint32_t *)(base + L.off_pq));
-  S.I.omp = b->omp;
+  S.I = make_dinst(inst, (const uint32_t *)(base + L.off_pq), b->omp);
   for (int k = 0; k < 2; ++k) {
     S.prio[k] = (int32_t *)(base + L.off_prio[k]);
     S.obj[k] = (int64_t *)(base + L.off_obj[k]);
