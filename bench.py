@@ -247,7 +247,7 @@ def bench_large(args):
         decodes += ev.decodes
         events.append(ev)
         per_event.append({"event": ev.event, "n_active": ev.n_active, "lds_slots": ev.lds_slots,
-                          "s": dt, "decodes_per_s": ev.decodes / dt,
+                          "narrow_lds": ev.narrow_lds, "s": dt, "decodes_per_s": ev.decodes / dt,
                           "decodes_redone_off_chip": ev.overflows})
         progress(f"large step {k + 1}: event {ev.event}, {ev.n_active} jobs, "
                  f"{ev.lds_slots} on-chip slots, {dt:.2f} s")

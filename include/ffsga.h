@@ -246,6 +246,11 @@ typedef struct {
   int64_t *elite_obj;               /* device [islands] */
   int32_t island_groups;            /* island groups the last ga_step ran (1: one stream,
                                        0: none yet; ga_set_island_groups) */
+  int32_t narrow_lds;               /* 1 if the last ga_step's generation kernel kept its
+                                       ready times in 16 bits: under the default decode rules
+                                       of the hybrid scheme, where that lets a compute unit
+                                       hold more waves of a population larger than the chip
+                                       holds at once (same results either way) */
 } ffs_ga;
 
 /* Device views of a GA state (pointers into its workspace). */

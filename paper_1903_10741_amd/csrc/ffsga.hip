@@ -308,12 +308,32 @@ enum : int { kDecOk = 0, kDecOverflow = 1, kDecInval = 2, kDecInfeasible = 3 };
 //   gene  [n]        the chromosome (input), at the start of prof's region (which holds
 //                    at least n words): it is dead once the decode has built the ranks,
 //                    before the profile is cleared
-struct Lds {
-  int32_t *gene, *rdy;
+//
+// The hybrid GA's generation and init kernels, under the default decode rules,
+// use a narrow form of the same layout (`LdsN`): rdy in 16 bits, clamped to
+// [0, 65535] when loaded ([n+2] halfwords at the start, then jobs and op). A
+// time of 65535 or more exceeds every on-chip profile (at most 32 768 slots), so
+// such a decode overflows anyway, and an op's end is read only at the job's next
+// stage, after the stage's overflow check; 0 for a job ready before RS changes
+// no start (every use takes a max with a machine's free time, at least 0). A
+// decode redone off chip lays the wide form over the same allocation.
+template <class R>
+struct LdsT {
+  int32_t *gene;
+  R *rdy;
   uint16_t *jobs, *op;
   uint32_t *rec;
   uint8_t *prof;
 };
+using Lds = LdsT<int32_t>;
+using LdsN = LdsT<uint16_t>;
+
+// Breeding scratch inside a decode's LDS (free until the decode builds its
+// ranks): n + 1 words and n halfwords.
+__device__ __forceinline__ int32_t *scratch32(const Lds &l) { return l.rdy; }
+__device__ __forceinline__ uint16_t *scratch16(const Lds &l) { return l.jobs; }
+__device__ __forceinline__ int32_t *scratch32(const LdsN &l) { return (int32_t *)l.jobs; }
+__device__ __forceinline__ uint16_t *scratch16(const LdsN &l) { return l.rdy; }
 
 // Words of one row-ring buffer: a chunk of kWave / o_s ops of o_s words each,
 // plus the record the op loop prefetches one past the chunk (read, never used).
@@ -328,6 +348,15 @@ __host__ __device__ inline size_t lds_bytes(int n, int cap) {
   const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0, gene = align_up((size_t)4 * n, 16);
   return lds_head(n) + (prof > gene ? prof : gene);
 }
+// The narrow form (LdsN), with room for the wide form of an off-chip redo.
+__host__ __device__ inline size_t lds_head_n(int n) {
+  return 3 * align_up((size_t)2 * n + 4, 16) + 4 * kRing;
+}
+__host__ __device__ inline size_t lds_bytes_n(int n, int cap) {
+  const size_t prof = cap > 0 ? align_up(cap, 16) + kWave : 0, gene = align_up((size_t)4 * n, 16);
+  const size_t narrow = lds_head_n(n) + (prof > gene ? prof : gene), redo = lds_head(n) + gene;
+  return narrow > redo ? narrow : redo;
+}
 
 __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   Lds l;
@@ -336,6 +365,17 @@ __device__ __forceinline__ Lds carve_lds(uint8_t *smem, int n) {
   l.jobs = (uint16_t *)(smem + a);
   l.op = (uint16_t *)(smem + a + b);
   l.rec = (uint32_t *)(smem + a + 2 * b);
+  l.prof = (uint8_t *)l.rec + 4 * kRing;
+  l.gene = (int32_t *)l.prof;
+  return l;
+}
+__device__ __forceinline__ LdsN carve_lds_n(uint8_t *smem, int n) {
+  LdsN l;
+  const size_t b = align_up((size_t)2 * n + 4, 16);
+  l.rdy = (uint16_t *)smem;
+  l.jobs = (uint16_t *)(smem + b);
+  l.op = (uint16_t *)(smem + 2 * b);
+  l.rec = (uint32_t *)(smem + 3 * b);
   l.prof = (uint8_t *)l.rec + 4 * kRing;
   l.gene = (int32_t *)l.prof;
   return l;
@@ -405,10 +445,13 @@ __device__ __forceinline__ bool live_at(const DInst &I, uint32_t jk, int s, bool
 //
 // RULES: false compiles the default rules only (no per-op rule test);
 // true reads I.rules (FFS_RULE_*). decode_core picks once per decode.
-template <int MAXM, bool PLAN, bool RULES, class Prof>
-__device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int64_t *obj_out,
+template <int MAXM, bool PLAN, bool RULES, class L, class Prof>
+__device__ int decode_core_rules(const DInst &I, const L &l, Prof &&prof, int64_t *obj_out,
                                  int64_t *work_out, int32_t *start_out, int32_t *mach_out,
                                  int32_t *span_max) {
+  using R = typename std::remove_pointer<decltype(l.rdy)>::type;
+  constexpr bool kNarrow = std::is_same<R, uint16_t>::value;
+  static_assert(!kNarrow || (!PLAN && !RULES), "narrow layout: default rules, no plan");
   const int lane = __lane_id();
   const int n = I.n;
   const u64 below = (1ull << lane) - 1;
@@ -431,8 +474,9 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     } else {
       const int j = ld_const(I.active, k);
       l.jobs[x] = (uint16_t)(k | min(ld_const(I.first, j), 15) << 12);
-      l.rdy[x] = ld_const(I.ready, j) - rs;  // may be negative: every use takes a max with
-                                             // a machine's free time, which is at least 0
+      // may be negative: every use takes a max with a machine's free time, at least 0
+      const int r = ld_const(I.ready, j) - rs;
+      l.rdy[x] = kNarrow ? (R)min(max(r, 0), 0xFFFF) : (R)r;
     }
   }
   if (ballot64(bad)) return kDecInval;
@@ -532,7 +576,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
     int vz;
     __asm__("v_mov_b32 %0, 0" : "=v"(vz));
     const uint16_t *opp = l.op + vz;
-    int32_t *rdy_at = l.rdy + opp[0];  // the current op's job
+    R *rdy_at = l.rdy + opp[0];  // the current op's job
     int rk1 = opp[1];                  // the next op's rank
     int ex = *rdy_at;                  // the current op's job's ready time
     // The stage's work sum, per lane (summed on the vector unit). Default rules:
@@ -561,7 +605,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       opp += 1;
       recp += os;
       const int rk2 = opp[1];
-      int32_t *const rdy_next = l.rdy + rk1;
+      R *const rdy_next = l.rdy + rk1;
       const int ex_next = *rdy_next;
       const uint32_t pq_next = *recp;
       // the previous op's profile words, formed while this op's keys reduce
@@ -619,7 +663,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
       cq = q;
       const int end = t + p;
       fr = ffs_writelane(end, mb, fr);
-      *rdy_at = PLAN ? end | (mb << 27) : end;
+      *rdy_at = (R)(PLAN ? end | (mb << 27) : end);
       stage_work = stage_work + cw;
       rdy_at = rdy_next;
       rk1 = rk2;
@@ -653,7 +697,7 @@ __device__ int decode_core_rules(const DInst &I, const Lds &l, Prof &&prof, int6
   int64_t tard = 0;
   int cmax = 0;
   for (int x = lane; x < n; x += kWave) {
-    const int c = l.rdy[x] + rs;
+    const int c = (int)l.rdy[x] + rs;
     const int late = c - ld_const(I.due_k, l.jobs[x] & 0xFFF);
     tard += late > 0 ? late : 0;
     cmax = max(cmax, c);
@@ -679,6 +723,15 @@ __device__ __forceinline__ int decode_core(const DInst &I, const Lds &l, Prof &&
                                                 span_max);
   return decode_core_rules<MAXM, PLAN, true>(I, l, prof, obj_out, work_out, start_out, mach_out,
                                              span_max);
+}
+// The narrow layout serves the default rules only (its callers check I.rules).
+template <int MAXM, bool PLAN, class Prof>
+__device__ __forceinline__ int decode_core(const DInst &I, const LdsN &l, Prof &&prof,
+                                           int64_t *obj_out, int64_t *work_out,
+                                           int32_t *start_out, int32_t *mach_out,
+                                           int32_t *span_max = nullptr) {
+  return decode_core_rules<MAXM, false, false>(I, l, prof, obj_out, work_out, start_out, mach_out,
+                                               span_max);
 }
 
 __device__ void flag_error(Header *h, int status) {
@@ -778,8 +831,9 @@ struct GaDev {
   size_t redo_stride;
   u64 seed, shop;
   // islands: the islands a generation launch covers, from island isl0 on (the
-  // whole population but for ga_step's island groups)
-  int32_t event, rows, cols, islands, mig_k, isl0;
+  // whole population but for ga_step's island groups); narrow: the generation
+  // and init kernels take the narrow LDS layout (LdsN)
+  int32_t event, rows, cols, islands, mig_k, isl0, narrow;
   uint32_t pc, pm;
 };
 
@@ -857,12 +911,13 @@ __device__ __forceinline__ int slot_of_block(int b, int K, int islands) {
 // purpose-2 block decides the swap mutation (Fig. 12). Both Philox blocks are
 // evaluated together on two lanes (the scalar unit, which the CU's waves
 // share, is the busier one). Every lane calls this.
-__device__ void build_child(const GaDev &A, int n, int i, int gen, const Lds &l,
+template <class L>
+__device__ void build_child(const GaDev &A, int n, int i, int gen, const L &l,
                             const int32_t *mine, const int32_t *other, int cross_idx,
                             int variant, bool store) {
   const int lane = __lane_id();
-  int32_t *first_pos = l.rdy;  // n + 1 words, then n halfwords in jobs: free before the decode
-  uint16_t *miss = l.jobs;
+  int32_t *first_pos = scratch32(l);  // free before the decode
+  uint16_t *miss = scratch16(l);
   u64 dw[4];
   {
     const bool xl = lane == 0;
@@ -911,7 +966,8 @@ __device__ void build_child(const GaDev &A, int n, int i, int gen, const Lds &l,
 // with correction, swap mutation. Crossover and mutation draw from Philox
 // block `variant` (0 for the plain generation; the screened generation's
 // candidates use 0..V-1). Every lane calls this.
-__device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l, int variant = 0,
+template <class L>
+__device__ void breed_child(const GaDev &A, int n, int i, int gen, const L &l, int variant = 0,
                             bool store = true) {
   const int K = A.rows * A.cols;
   // Pair (Fig. 10 is not available; reading: horizontal neighbours
@@ -934,9 +990,10 @@ __device__ void breed_child(const GaDev &A, int n, int i, int gen, const Lds &l,
 
 // Generation 0 of slot i: Fisher-Yates over 1..n, draw d from word d % 4 of
 // block d / 4 of purpose 0; the result goes to l.gene and A.prio_out.
-__device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
+template <class L>
+__device__ void init_child(const GaDev &A, int n, int i, const L &l) {
   const int lane = __lane_id();
-  uint32_t *hi = (uint32_t *)l.rdy;  // n - 1 high words (rdy is scratch before the decode)
+  uint32_t *hi = (uint32_t *)scratch32(l);  // n - 1 high words (scratch before the decode)
   for (int k = lane; k < n; k += kWave) l.gene[k] = k + 1;
   const int n_blocks = (n - 1 + 3) / 4;
   for (int b = lane; b < n_blocks; b += kWave) {
@@ -962,9 +1019,10 @@ __device__ void init_child(const GaDev &A, int n, int i, const Lds &l) {
 
 // Decode l.gene for slot i (its genes are also in A.prio_out) and record the
 // outcome: the objective, the work count, or an overflow entry `tag` for the
-// off-chip redo, which the wave does itself when it has a profile of its own.
-template <int MAXM>
-__device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap, const Lds &l,
+// off-chip redo, which the wave does itself when it has a profile of its own
+// (in the wide layout, laid over the same LDS: both start at rdy).
+template <int MAXM, class L>
+__device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap, const L &l,
                                   int tag, int32_t *span = nullptr) {
   int64_t work = 0;
   int st = decode_core<MAXM, false>(I, l, LdsProfile{l.prof, cap}, A.obj_out + i, &work, nullptr,
@@ -975,12 +1033,13 @@ __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap
     if (span) atomicMax(span, cap + 1);
   }
   if (st == kDecOverflow && A.redo_prof) {
+    const Lds lw = carve_lds((uint8_t *)l.rdy, I.n);
     const int32_t *src = A.prio_out + (size_t)i * I.n;
-    for (int k = __lane_id(); k < I.n; k += kWave) l.gene[k] = src[k];  // this lane's own stores
+    for (int k = __lane_id(); k < I.n; k += kWave) lw.gene[k] = src[k];  // this lane's own stores
     __asm__ volatile("" ::: "memory");
     work = 0;
     const GlobalProfile gp{A.redo_prof + A.redo_stride * i, offchip_cap(I.horizon)};
-    st = decode_core<MAXM, false>(I, l, gp, A.obj_out + i, &work, nullptr, nullptr);
+    st = decode_core<MAXM, false>(I, lw, gp, A.obj_out + i, &work, nullptr, nullptr);
     if (st == kDecOverflow) st = kDecInval;  // the horizon bound was wrong: cannot happen
   }
   if (st == kDecOk) {
@@ -1202,9 +1261,15 @@ __global__ __launch_bounds__(64) void ga_generation_kernel(DInst I, GaDev A, int
   extern __shared__ __align__(16) uint8_t smem[];
   const int K = A.rows * A.cols;
   const int i = A.isl0 * K + slot_of_block(blockIdx.x, K, A.islands);
-  const Lds l = carve_lds(smem, I.n);
-  breed_child(A, I.n, i, gen, l);
-  decode_and_record<MAXM>(I, A, i, cap, l, i);
+  if (A.narrow) {  // the narrow layout (lds_bytes_n): default rules only
+    const LdsN l = carve_lds_n(smem, I.n);
+    breed_child(A, I.n, i, gen, l);
+    decode_and_record<MAXM>(I, A, i, cap, l, i);
+  } else {
+    const Lds l = carve_lds(smem, I.n);
+    breed_child(A, I.n, i, gen, l);
+    decode_and_record<MAXM>(I, A, i, cap, l, i);
+  }
 }
 
 // Generation 0. span: null, or where the longest schedule is recorded
@@ -1213,9 +1278,20 @@ template <int MAXM>
 __global__ __launch_bounds__(64) void ga_init_kernel(DInst I, GaDev A, int cap, int32_t *span) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int i = blockIdx.x;
-  const Lds l = carve_lds(smem, I.n);
-  init_child(A, I.n, i, l);
-  decode_and_record<MAXM>(I, A, i, cap, l, i, span);
+  if (A.narrow) {  // the narrow layout (lds_bytes_n): default rules only
+    const LdsN l = carve_lds_n(smem, I.n);
+    init_child(A, I.n, i, l);
+    decode_and_record<MAXM>(I, A, i, cap, l, i, span);
+  } else {
+    const Lds l = carve_lds(smem, I.n);
+    init_child(A, I.n, i, l);
+    decode_and_record<MAXM>(I, A, i, cap, l, i, span);
+  }
+}
+
+// LDS of the generation and init kernels in the layout they take.
+size_t lds_bytes_gen(const ffs_instance *in, int cap, bool narrow) {
+  return narrow ? lds_bytes_n(in->n_active, cap) : lds_bytes(in->n_active, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -2043,6 +2119,7 @@ __device__ __forceinline__ GaDev slot_ga(const BatchSlot &S, const BatchArgs &B,
   A.cols = B.cols;
   A.islands = B.islands;
   A.isl0 = 0;
+  A.narrow = 0;
   A.mig_k = B.mig_k;
   A.pc = B.pc;
   A.pm = B.pm;
@@ -2859,6 +2936,7 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
   A.cols = ga->params.cols;
   A.islands = ga->params.islands;
   A.isl0 = 0;
+  A.narrow = 0;
   A.mig_k = ga->params.mig_k;
   A.pc = ga->params.pc;
   A.pm = ga->params.pm;
@@ -2904,6 +2982,26 @@ int waves_per_cu(size_t bytes) {
   return b;
 }
 
+int n_cus() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return v;
+}
+
+// Whether the generation and init kernels take the narrow layout: under the
+// default rules, and only where it lets a compute unit hold more waves of a
+// population that the chip cannot hold at once in the wide layout (otherwise
+// the narrow form's extra masking buys nothing).
+template <int MAXM>
+bool use_narrow(const ffs_instance *in, int cap, int pop) {
+  if (in->decode_rules != 0) return false;
+  const int ww = waves_per_cu<MAXM>(lds_bytes(in->n_active, cap));
+  const int wn = waves_per_cu<MAXM>(lds_bytes_n(in->n_active, cap));
+  return wn > ww && (int64_t)pop > (int64_t)ww * n_cus();
+}
+
 template <int MAXM>
 int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStream_t stream,
                  bool auto_cap) {
@@ -2911,7 +3009,7 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
   GaDev A = make_gadev(ga, L, 1);  // generation 0 is written to buffer 0
   const int pop = ga->pop, cap = ga->lds_slots, n = ga->n_genes;
   const int K = ga->params.rows * ga->params.cols;
-  const bool xy = ga->params.encoding == 1;
+  const bool xy = ga->params.encoding == 1, hybrid = ga->params.scheme == FFS_GA_HYBRID;
   int rc;
   if (xy) {
     if ((rc = build_xy_table(in, L.xyop, L.xyg0, stream))) return rc;
@@ -2919,10 +3017,11 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
                lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap), stream, d,
                XyTab{L.xyop, L.xyg0, in->n_ops}, A, cap) != hipSuccess)
       return FFS_E_DEVICE;
-  } else if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes(n, cap),
-                    stream, d, A, cap, auto_cap ? &L.hdr->span_max : (int32_t *)nullptr) !=
-             hipSuccess) {
-    return FFS_E_DEVICE;
+  } else {
+    A.narrow = hybrid && use_narrow<MAXM>(in, cap, pop);
+    if (launch(1, ga_init_kernel<MAXM>, dim3(pop), dim3(kWave), lds_bytes_gen(in, cap, A.narrow),
+               stream, d, A, cap, auto_cap ? &L.hdr->span_max : (int32_t *)nullptr) != hipSuccess)
+      return FFS_E_DEVICE;
   }
   rc = ga_overflow<MAXM>(in, L, 0, cap, stream, xy);
   if (rc) return rc;
@@ -2941,13 +3040,15 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
     Header host;
     if ((rc = read_header(L.hdr, &host, stream))) return rc;
     const int64_t span = host.span_max;
-    int64_t lo = (int64_t)align_up((size_t)(span + span / 16 + 64), 64);
+    int64_t lo = (int64_t)align_up((size_t)(span + span / 64 + 64), 64);
     if (lo > cap) lo = cap;
-    const int w = waves_per_cu<MAXM>(lds_bytes(n, (int)lo));
+    // the layout the generations will take at lo sets the bytes per slot count
+    const bool narrow = hybrid && use_narrow<MAXM>(in, (int)lo, pop);
+    const int w = waves_per_cu<MAXM>(lds_bytes_gen(in, (int)lo, narrow));
     int64_t a = lo / 64, b = cap / 64;  // waves_per_cu falls as the slots grow
     while (w > 0 && a < b) {
       const int64_t m = (a + b + 1) / 2;
-      if (waves_per_cu<MAXM>(lds_bytes(n, (int)(m * 64))) >= w)
+      if (waves_per_cu<MAXM>(lds_bytes_gen(in, (int)(m * 64), narrow)) >= w)
         a = m;
       else
         b = m - 1;
@@ -3042,7 +3143,7 @@ bool migrate(const ffs_ga_params &p, const GaLayout &L, int cur, int n, hipStrea
 // holds islands [islands * g / G, islands * (g + 1) / G).
 template <int MAXM>
 int ga_step_groups(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, int32_t n_gen,
-                   hipStream_t stream, int G, size_t shmem, const Screen *scr) {
+                   hipStream_t stream, int G, size_t shmem, const Screen *scr, bool narrow) {
   std::lock_guard<std::mutex> lk(g_group_mu);
   GroupStreams *GS = nullptr;
   int rc = group_streams(&GS);
@@ -3074,6 +3175,7 @@ int ga_step_groups(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, int32_
       GaDev A = make_gadev(ga, L, cur);
       A.isl0 = i0;
       A.islands = i1 - i0;
+      A.narrow = narrow;
       const dim3 grid((unsigned)((i1 - i0) * K));
       const hipError_t e =
           scr ? launch(5, ga_screened_kernel<MAXM>, grid, dim3(kWave), shmem, sg, d, A, gen, cap,
@@ -3107,8 +3209,12 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
   const int K = ga->params.rows * ga->params.cols;
   const bool xy = ga->params.encoding == 1;
   const XyTab T{L.xyop, L.xyg0, in->n_ops};
+  // shmem: the screened and comparison kernels; shmem_gen: the generation kernel
   const size_t shmem = xy ? lds_bytes_xy(in->n_active, in->n_ops, in->n_stages, in->o_max, cap)
                           : lds_bytes(in->n_active, cap);
+  const bool narrow = !xy && ga->params.scheme == FFS_GA_HYBRID && use_narrow<MAXM>(in, cap, pop);
+  const size_t shmem_gen = xy ? shmem : lds_bytes_gen(in, cap, narrow);
+  ga->narrow_lds = narrow && !scr;
   // Island groups for the hybrid GA whose overflowed decodes are redone by their
   // own waves (the overflow kernel's list belongs to the whole population).
   if (ga->params.scheme == FFS_GA_HYBRID && (cap >= in->horizon || L.inline_redo)) {
@@ -3117,7 +3223,8 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     if (G > ga->params.islands) G = ga->params.islands;
     if (G > 1) {
       ga->island_groups = G;
-      return ga_step_groups<MAXM>(ga, in, L, n_gen, stream, G, shmem, scr);
+      return ga_step_groups<MAXM>(ga, in, L, n_gen, stream, G, scr ? shmem : shmem_gen, scr,
+                                  narrow && !scr);
     }
   }
   ga->island_groups = 1;
@@ -3125,6 +3232,7 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
     const int gen = ga->generation + 1;
     const int cur = ga->cur;
     GaDev A = make_gadev(ga, L, cur);
+    A.narrow = narrow;
     hipError_t e;
     const int32_t scheme = ga->params.scheme;
     if (scheme == FFS_GA_CLASSICAL) {
@@ -3143,8 +3251,8 @@ int ga_step_impl(ffs_ga *ga, const ffs_instance *in, int32_t n_gen, hipStream_t 
       e = launch(1, ga_generation_xy_kernel, dim3(pop), dim3(kWave), shmem, stream, d, T, A, gen,
                  cap);
     else
-      e = launch(1, ga_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem, stream, d, A, gen,
-                 cap);
+      e = launch(1, ga_generation_kernel<MAXM>, dim3(pop), dim3(kWave), shmem_gen, stream, d, A,
+                 gen, cap);
     if (e != hipSuccess) return FFS_E_DEVICE;
     int rc = ga_overflow<MAXM>(in, L, 1 - cur, cap, stream, xy);
     if (rc) return rc;
@@ -3640,6 +3748,7 @@ int ga_init(ffs_ga *ga, const ffs_instance *inst, const ffs_ga_params *params, u
   ga->generation = 0;
   ga->cur = 0;
   ga->island_groups = 0;
+  ga->narrow_lds = 0;
   ga->workspace = workspace;
   ga->workspace_bytes = workspace_bytes;
   ga->lds_slots = cap;

@@ -75,7 +75,7 @@ class FfsGa(ctypes.Structure):
         ("lds_slots", ctypes.c_int32), ("n_jobs", ctypes.c_int32), ("horizon", ctypes.c_int32),
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("prio", _vp * 2), ("obj", _vp * 2), ("elite", _vp), ("elite_obj", _vp),
-        ("island_groups", ctypes.c_int32),
+        ("island_groups", ctypes.c_int32), ("narrow_lds", ctypes.c_int32),
     ]
 
 

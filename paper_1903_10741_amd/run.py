@@ -29,6 +29,7 @@ class EventResult:
     decodes: int = 0               # the GA's decodes plus the executed plan's
     overflows: int = 0             # the GA's decodes redone off chip
     island_groups: int = 1         # island groups the event's ga_step ran concurrently
+    narrow_lds: int = 0            # 1 if its generations kept ready times in 16 bits
 
 
 @dataclass
@@ -84,7 +85,8 @@ class EventLoop:
         ev = EventResult(e, int(d.s.rs), d.n_active, best_prio=prio, best_obj=obj,
                          work=ga.view()["work"].clone(), lds_slots=int(ga.ga.lds_slots),
                          decodes=(1 + self.gens) * ga.ga.pop + 1, overflows=ga.overflows(),
-                         island_groups=int(ga.ga.island_groups))
+                         island_groups=int(ga.ga.island_groups),
+                         narrow_lds=int(ga.ga.narrow_lds))
         if self.keep_instances:
             ev.instance = d
         if e + 1 < self.n_events:

@@ -142,6 +142,33 @@ def test_ga_overflow_tier_in_the_loop():
     _same(_state(ga), st, "overflow GA")
 
 
+def test_ga_narrow_layout_with_inline_redo():
+    """200 jobs, 6144 individuals and 5440-5760 on-chip slots (about 7.5 KB of LDS
+    per wave): 16-bit ready times save 400 bytes a wave, which at some of these
+    sizes lets a compute unit hold one more wave, and 6144 individuals are more
+    than the chip holds at once, so there the generation kernels take the narrow
+    layout (at least one size must). The schedules outgrow the slots and each is
+    redone by its own wave in the wide layout over the same LDS (6144 off-chip
+    profiles fit the 1 GiB the workspace allows). Whole state against the oracle
+    at every size."""
+    torch, ffsga = _ffs()
+    wl = W.config3(0)
+    gp = W.GaParams(48, 8, 16, mig_interval=2, mig_k=2)
+    st = oracle.ga_run(wl.initial, gp, wl.seed, wl.shop, 0, 3, n_threads=8)
+    d = ffsga.DeviceInstance.from_host(wl.initial)
+    narrow = []
+    for slots in (5440, 5504, 5568, 5632, 5696, 5760):
+        _say("narrow layout, inline redo: 200 jobs, pop 6144, slots", slots)
+        ga = ffsga.GA(d, ffsga.GaConfig.of(gp, lds_slots=slots), wl.seed, wl.shop, 0)
+        ga.step(3)
+        ga.status()
+        assert ga.overflows() > 0
+        narrow.append(int(ga.ga.narrow_lds))
+        _same(_state(ga), st, f"{slots} slots, narrow {narrow[-1]}")
+    _say("narrow layout taken at", narrow)
+    assert any(narrow)
+
+
 def test_ga_odd_island_shape_and_tiny_genes():
     """Odd torus sides leave unpaired slots; n_active = 1 and 2 have no or one cut."""
     torch, ffsga = _ffs()
