@@ -219,7 +219,7 @@ typedef struct {
  * gets FFS_E_UNSUPPORTED): ga_init decodes generation 0 with as many on-chip
  * slots as one workgroup's LDS holds (at most 32768, no more than the horizon
  * needs) and records the longest schedule (end - RS). Every later generation
- * keeps that schedule plus 1/16 of it and 64 slots on chip, widened to the
+ * keeps that schedule plus 1/64 of it and 64 slots on chip, widened to the
  * most slots (a multiple of 64, at most the sizing decode's) at which a compute
  * unit still holds as many waves of the generation kernel (the runtime's
  * occupancy figure), so long schedules stay on chip and short ones leave LDS for

@@ -3034,7 +3034,7 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
              L.hdr) != hipSuccess)
     return FFS_E_DEVICE;
   if (auto_cap) {
-    // Later generations: generation 0's longest schedule plus 1/16 and 64 slots,
+    // Later generations: generation 0's longest schedule plus 1/64 and 64 slots,
     // then widened to the most slots (at most the sizing decode's) that keep as
     // many waves per compute unit.
     Header host;
