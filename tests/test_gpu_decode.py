@@ -151,6 +151,31 @@ def test_decode_full_population_config3_sampled():
     assert (got > 0).all()
 
 
+@pytest.mark.parametrize("rules", [0, 1])
+def test_decode_late_first_stages_of_twenty(rules):
+    """20 stages, rescheduled where some jobs have finished 15 or more stages: the
+    16-bit job records hold a first stage only up to 15, so from stage 15 on such
+    jobs are looked up; with the default rules and with the FIFO stage order (whose
+    compaction tests the same records)."""
+    _say("decode, 20 stages, late first stages, rules", rules)
+    g, om = 20, 2
+    inst = W.random_instance(17, n_jobs=40, n_stages=g, machines=om, p_max=10, percent=70)
+    prio = W.random_population(18, 1, inst.n_active)[0]
+    _, s, m, _ = oracle.decode(inst, prio, want_schedule=True)
+    rs = int(np.median(s[:, 16])) + 1
+    rng = np.random.default_rng(19)
+    k = 6
+    proc = rng.integers(1, 11, size=(k, g, om)).astype(np.int32)
+    power = np.broadcast_to(np.asarray(inst.power)[:1], (k, g, om)).astype(np.int32)
+    nxt = W.Instance.from_fields(oracle.reschedule(inst, s, m, rs, proc, power,
+                                                   np.full(k, rs, np.int32),
+                                                   np.full(k, rs + 200, np.int32)))
+    nxt.decode_rules = rules
+    firsts = np.asarray(nxt.first_stage)[np.asarray(nxt.active)]
+    assert (firsts >= 15).any() and (firsts < 15).any(), firsts
+    _compare(nxt, W.random_population(20 + rules, 48, nxt.n_active))
+
+
 def test_decode_empty_active_set():
     _say("decode with no active job")
     torch, ffsga = _ffs()
