@@ -1316,6 +1316,7 @@ struct XyTab {
 //   fm   [g*om]   machine free times (rdy and fm live in registers instead
 //                 when there are at most 128 jobs and 64 machine slots)
 //   then one region used twice: until Z is built, the priority genes gy [R]
+//   (once the heads are built, each gene's place in Z)
 //   and head [R+1] (per priority value y: k | len << 24 when gene k starts a
 //   chain of len genes of one job whose running minimum of y is y, else 0);
 //   from then on the power profile prof [cap+64]. A decode redone off chip
@@ -1417,7 +1418,11 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     if (hk >= 0) l.head[m] = hk | (k1 - hk) << 24;
   }
   __asm__ volatile("" ::: "memory");
-  // Z: chains by decreasing head value; each op's record
+  // Z: chains by decreasing head value. First each gene's place in Z (into the
+  // priority genes' words, dead once the heads are built: LDS only), then each
+  // op's record, one gene per lane, so the table reads of different genes are
+  // in flight together instead of one chain element after another.
+  int32_t *zpos = l.gy;
   int base = 0;
   for (int y0 = R; y0 >= 1; y0 -= kWave) {
     const int y = y0 - lane;
@@ -1425,13 +1430,15 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
     const int len = (int)((uint32_t)h >> 24), k = h & 0xFFFFFF;
     const int incl = wave_scan_incl(len);
     const int pos = base + incl - len;
-    for (int i = 0; i < len; ++i) {
-      const int kk = k + i, op = ld_const(T.op, kk), x = op & 0xFFFFF, s = op >> 20;
-      const int m = l.gx[kk];
-      const uint32_t pq = ld_const(I.pq, ((size_t)x * I.g + s) * I.omp + m);
-      l.zrec[pos + i] = make_int2(x | (s * I.om + m) << 12, (int)pq);
-    }
+    for (int i = 0; i < len; ++i) zpos[k + i] = pos + i;
     base += __builtin_amdgcn_readlane(incl, kWave - 1);
+  }
+  __asm__ volatile("" ::: "memory");
+  for (int kk = lane; kk < R; kk += kWave) {
+    const int op = ld_const(T.op, kk), x = op & 0xFFFFF, s = op >> 20;
+    const int m = l.gx[kk];
+    const uint32_t pq = ld_const(I.pq, ((size_t)x * I.g + s) * I.omp + m);
+    l.zrec[zpos[kk]] = make_int2(x | (s * I.om + m) << 12, (int)pq);
   }
   if (lane == 0) l.zrec[R] = make_int2(0, 0);  // spare record: the loop reads one past the last
   int rv0 = 0, rv1 = 0, fmv = 0;
