@@ -1298,12 +1298,13 @@ size_t lds_bytes_gen(const ffs_instance *in, int cap, bool narrow) {
 // The paper's own chromosome: target machines X and operation priorities Y
 // (Section 4.3, eqs. (10)-(12)). Only unfrozen ops carry genes, R of them,
 // row-major over the active jobs (gene k <-> op xyop[k] = x | s << 20 of
-// active job x; job x's genes are [xyg0[x], xyg0[x+1])). A chromosome is
+// active job x, with the stage's machine count o_s as (o_s - 1) << 27; job x's
+// genes are [xyg0[x], xyg0[x+1])). A chromosome is
 // 2R ints: the R machines, then the R priorities (a permutation of 1..R,
 // larger = higher).
 // ---------------------------------------------------------------------------
 struct XyTab {
-  const int32_t *op;   // [R]: x | s << 20
+  const int32_t *op;   // [R]: x | s << 20 | (o_s - 1) << 27
   const int32_t *g0;   // [n + 1]
   int32_t R;
 };
@@ -1392,8 +1393,8 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   // (each value counted once)
   int bad = 0;
   for (int k = lane; k < R; k += kWave) {
-    const int x = l.gx[k], s = ld_const(T.op, k) >> 20;
-    if (x < 0 || x >= ld_const(I.nm, s)) bad = 1;
+    const int x = l.gx[k], os = (ld_const(T.op, k) >> 27) + 1;
+    if (x < 0 || x >= os) bad = 1;
     const int y = l.gy[k];
     if (y < 1 || y > R) bad = 1;
     else atomicAdd(&l.head[y], 1);
@@ -1435,7 +1436,7 @@ __device__ int decode_xy_core_t(const DInst &I, const XyTab &T, const LdsXy &l, 
   }
   __asm__ volatile("" ::: "memory");
   for (int kk = lane; kk < R; kk += kWave) {
-    const int op = ld_const(T.op, kk), x = op & 0xFFFFF, s = op >> 20;
+    const int op = ld_const(T.op, kk), x = op & 0xFFFFF, s = (op >> 20) & 0x7F;
     const int m = l.gx[kk];
     const uint32_t pq = ld_const(I.pq, ((size_t)x * I.g + s) * I.omp + m);
     l.zrec[zpos[kk]] = make_int2(x | (s * I.om + m) << 12, (int)pq);
@@ -1576,9 +1577,11 @@ __device__ __forceinline__ int decode_xy_core(const DInst &I, const XyTab &T, co
 }
 
 // Gene/op table of an instance (one block of 1024 threads): the active jobs'
-// gene offsets by a block prefix sum, then each gene's (x, stage).
+// gene offsets by a block prefix sum, then each gene's (x, stage, machines of
+// the stage), so a gene's machine range needs no second read.
 __global__ __launch_bounds__(1024) void xy_table_kernel(const int32_t *first, const int32_t *active,
-                                                        int n, int g, int32_t *op, int32_t *g0) {
+                                                        const int32_t *nm, int n, int g,
+                                                        int32_t *op, int32_t *g0) {
   __shared__ int32_t part[1024];
   const int t = threadIdx.x, per = (n + 1023) / 1024, x0 = t * per, x1 = min(n, x0 + per);
   int sum = 0;
@@ -1594,7 +1597,8 @@ __global__ __launch_bounds__(1024) void xy_table_kernel(const int32_t *first, co
   int k = part[t] - sum;
   for (int x = x0; x < x1; ++x) {
     g0[x] = k;
-    for (int s = first[active[x]]; s < g; ++s) op[k++] = x | s << 20;
+    for (int s = first[active[x]]; s < g; ++s)
+      op[k++] = x | s << 20 | (min(max(nm[s], 1), 16) - 1) << 27;  // 1 <= o_s <= 16
   }
   if (t == 1023) g0[n] = part[1023];
 }
@@ -1676,7 +1680,7 @@ __device__ void init_child_xy(const GaDev &A, const DInst &I, const XyTab &T, in
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = 4 * b + u;
-      if (k < R) l.gx[k] = (int)draw_below(w[u], (uint32_t)ld_const(I.nm, ld_const(T.op, k) >> 20));
+      if (k < R) l.gx[k] = (int)draw_below(w[u], (uint32_t)(ld_const(T.op, k) >> 27) + 1u);
     }
   }
   uint32_t *hi = (uint32_t *)l.zrec;  // R - 1 high words
@@ -1772,7 +1776,7 @@ __device__ void breed_child_xy(const GaDev &A, const DInst &I, const XyTab &T, i
       for (int u = 0; u < 4; ++u) {
         const int k = 4 * b + u;
         if (k >= R) break;
-        const int o = ld_const(I.nm, ld_const(T.op, k) >> 20);
+        const int o = (ld_const(T.op, k) >> 27) + 1;
         if (o > 1) l.gx[k] = (l.gx[k] + 1 + (int)draw_below(v[u], (uint32_t)(o - 1))) % o;
       }
     }
@@ -2972,7 +2976,7 @@ int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hip
 
 int build_xy_table(const ffs_instance *in, int32_t *op, int32_t *g0, hipStream_t stream) {
   return launch(-1, xy_table_kernel, dim3(1), dim3(1024), 0, stream, in->first_stage, in->active,
-                in->n_active, in->n_stages, op, g0) == hipSuccess
+                in->n_machines, in->n_active, in->n_stages, op, g0) == hipSuccess
              ? FFS_OK
              : FFS_E_DEVICE;
 }
