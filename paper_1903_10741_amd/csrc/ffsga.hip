@@ -1065,9 +1065,13 @@ __device__ void wave_arg(int64_t &v, int &idx) {
   }
 }
 
-// Replacement of island I by one wave (same rule as replace_island).
+// Replacement of island I by one wave (same rule as replace_island): the best
+// child becomes the best-in-history if it beats it, and the best-in-history
+// replaces the worst child. The genes kept are read once and stored to both
+// places (a slot that is both best and worst gets its own genes back).
 __device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
   const int lane = __lane_id(), base = I * K;
+  const int64_t old = A.elite_obj[I];  // read beside the objectives
   int64_t bv = LLONG_MAX, wv = LLONG_MIN;
   int b = INT_MAX, w = INT_MAX;
   for (int k = lane; k < K; k += kWave) {
@@ -1083,17 +1087,18 @@ __device__ void replace_island_wave(const GaDev &A, int I, int K, int n) {
   }
   wave_arg<false>(bv, b);
   wave_arg<true>(wv, w);
-  const int64_t old = A.elite_obj[I];
-  if (bv < old) {
-    for (int k = lane; k < n; k += kWave)
-      A.elite[(size_t)I * n + k] = A.prio_out[(size_t)(base + b) * n + k];
-    if (lane == 0) A.elite_obj[I] = bv;
+  const bool better = bv < old;
+  int32_t *elite = A.elite + (size_t)I * n, *worst = A.prio_out + (size_t)(base + w) * n;
+  const int32_t *keep = better ? A.prio_out + (size_t)(base + b) * n : elite;
+  for (int k = lane; k < n; k += kWave) {
+    const int32_t v = keep[k];
+    if (better) elite[k] = v;
+    worst[k] = v;
   }
-  __asm__ volatile("" ::: "memory");
-  // each lane reads back only the elite words it wrote itself
-  for (int k = lane; k < n; k += kWave)
-    A.prio_out[(size_t)(base + w) * n + k] = A.elite[(size_t)I * n + k];
-  if (lane == 0) A.obj_out[base + w] = bv < old ? bv : old;
+  if (lane == 0) {
+    if (better) A.elite_obj[I] = bv;
+    A.obj_out[base + w] = better ? bv : old;
+  }
 }
 
 
