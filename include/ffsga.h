@@ -217,10 +217,11 @@ typedef struct {
 
 /* ffs_ga_params.lds_slots = FFS_LDS_AUTO (job-priority vectors only; encoding 1
  * gets FFS_E_UNSUPPORTED): ga_init decodes generation 0 with as many on-chip
- * slots as one workgroup's LDS holds (at most 32768, no more than the horizon
- * needs) and records the longest schedule (end - RS). Every later generation
+ * slots as one workgroup's LDS holds (at most 16384, no more than the horizon
+ * needs; a longer schedule is redone off chip) and records the longest schedule
+ * (end - RS). Every later generation
  * keeps that schedule plus 1/64 of it and 64 slots on chip, widened to the
- * most slots (a multiple of 64, at most the sizing decode's) at which a compute
+ * most slots (a multiple of 64, at most 32768) at which a compute
  * unit still holds as many waves of the generation kernel (the runtime's
  * occupancy figure), so long schedules stay on chip and short ones leave LDS for
  * more waves. ga_init then synchronises its stream once and ffs_ga.lds_slots

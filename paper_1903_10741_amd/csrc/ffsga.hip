@@ -774,13 +774,14 @@ __global__ __launch_bounds__(64) void decode_kernel(DInst I, const int32_t *__re
 }
 
 // Redo the decodes listed as overflowed with a global-memory profile of
-// `horizon` slots per block; the last block to finish clears the list.
+// `horizon` slots per block; the last block to finish clears the list. span:
+// null, or where the longest schedule is recorded (FFS_LDS_AUTO's sizing).
 template <int MAXM>
 __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__restrict__ prio,
                                                       int64_t *obj, int64_t *work, int32_t *start,
                                                       int32_t *mach, Header *hdr,
                                                       const int32_t *ovf_list, uint8_t *gprof,
-                                                      size_t gstride) {
+                                                      size_t gstride, int32_t *span) {
   extern __shared__ __align__(16) uint8_t smem[];
   Lds l = carve_lds(smem, I.n);
   const int count = __hip_atomic_load(&hdr->ovf_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -793,8 +794,9 @@ __global__ __launch_bounds__(64) void overflow_kernel(DInst I, const int32_t *__
     const size_t plan = (size_t)i * I.n_jobs * I.g;
     int64_t w = 0;
     int64_t *wp = work ? work + i : &w;
-    const int st = start ? decode_core<MAXM, true>(I, l, prof, obj + i, wp, start + plan, mach + plan)
-                         : decode_core<MAXM, false>(I, l, prof, obj + i, wp, nullptr, nullptr);
+    const int st = start ? decode_core<MAXM, true>(I, l, prof, obj + i, wp, start + plan, mach + plan,
+                                                   span)
+                         : decode_core<MAXM, false>(I, l, prof, obj + i, wp, nullptr, nullptr, span);
     if (st == kDecOk && !work && __lane_id() == 0) atomicAdd(&hdr->work, (unsigned long long)w);
     if (st != kDecOk) {
       if (__lane_id() == 0) obj[i] = -1;
@@ -1039,7 +1041,7 @@ __device__ void decode_and_record(const DInst &I, const GaDev &A, int i, int cap
     __asm__ volatile("" ::: "memory");
     work = 0;
     const GlobalProfile gp{A.redo_prof + A.redo_stride * i, offchip_cap(I.horizon)};
-    st = decode_core<MAXM, false>(I, lw, gp, A.obj_out + i, &work, nullptr, nullptr);
+    st = decode_core<MAXM, false>(I, lw, gp, A.obj_out + i, &work, nullptr, nullptr, span);
     if (st == kDecOverflow) st = kDecInval;  // the horizon bound was wrong: cannot happen
   }
   if (st == kDecOk) {
@@ -2770,7 +2772,7 @@ int run_decode(const ffs_instance *in, const int32_t *prio, int32_t pop, int64_t
   if (cap < in->horizon) {
     e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave), lds_bytes(in->n_active, 0),
                stream, d, prio, obj, work, start, mach, L.hdr, (const int32_t *)L.ovf_list, L.gprof,
-               L.gstride);
+               L.gstride, (int32_t *)nullptr);
     if (e != hipSuccess) return FFS_E_DEVICE;
   }
   return FFS_OK;
@@ -2904,16 +2906,18 @@ GaLayout ga_layout(void *ws, const ffs_instance *in, const ffs_ga_params *p, int
 // off-chip profiles.
 int layout_cap(const ffs_ga_params *p, int cap) { return p->lds_slots == FFS_LDS_AUTO ? 0 : cap; }
 
-// On-chip slots of the sizing decode of FFS_LDS_AUTO: as many as one
-// workgroup's LDS holds next to the chromosome's arrays, at most kProbeSlots
-// (longer schedules then keep that many, the rest of each decode going off
-// chip) and no more than the horizon needs.
-constexpr int64_t kProbeSlots = 32768;
-int probe_cap(const ffs_instance *in) {
+// On-chip slots FFS_LDS_AUTO works with: as many as one workgroup's LDS holds
+// next to the chromosome's arrays, at most `limit` and no more than the horizon
+// needs. The sizing decode of generation 0 keeps at most kProbeSlots (a longer
+// schedule is decoded again off chip, which records its length too, and the
+// smaller allocation lets more of its waves run at once); later generations may
+// keep up to kAutoSlots.
+constexpr int64_t kProbeSlots = 16384, kAutoSlots = 32768;
+int probe_cap(const ffs_instance *in, int64_t limit = kProbeSlots) {
   const int64_t h = (int64_t)align_up((size_t)in->horizon, 64);
   const int64_t room = (int64_t)max_lds_bytes() - (int64_t)lds_head(in->n_active) - kWave;
   int64_t cap = room / 64 * 64;
-  if (cap > kProbeSlots) cap = kProbeSlots;
+  if (cap > limit) cap = limit;
   if (cap > h) cap = h;
   return (int)(cap < 64 ? 64 : cap);
 }
@@ -2961,7 +2965,7 @@ GaDev make_gadev(const ffs_ga *ga, const GaLayout &L, int in_buf) {
 
 template <int MAXM>
 int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hipStream_t stream,
-                bool xy = false) {
+                bool xy = false, int32_t *span = nullptr) {
   if (cap >= in->horizon || L.inline_redo) return FFS_OK;
   const DInst d = make_dinst(in, L.pq);
   hipError_t e;
@@ -2975,7 +2979,7 @@ int ga_overflow(const ffs_instance *in, const GaLayout &L, int buf, int cap, hip
     e = launch(3, overflow_kernel<MAXM>, dim3(kFixBlocks), dim3(kWave),
                lds_bytes(in->n_active, 0), stream, d, (const int32_t *)L.prio[buf],
                L.obj[buf], (int64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, L.hdr,
-               (const int32_t *)L.ovf_list, L.gprof, L.gstride);
+               (const int32_t *)L.ovf_list, L.gprof, L.gstride, span);
   return e == hipSuccess ? FFS_OK : FFS_E_DEVICE;
 }
 
@@ -3039,7 +3043,7 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
                stream, d, A, cap, auto_cap ? &L.hdr->span_max : (int32_t *)nullptr) != hipSuccess)
       return FFS_E_DEVICE;
   }
-  rc = ga_overflow<MAXM>(in, L, 0, cap, stream, xy);
+  rc = ga_overflow<MAXM>(in, L, 0, cap, stream, xy, auto_cap ? &L.hdr->span_max : nullptr);
   if (rc) return rc;
   if (launch(-1, elite_init_kernel, dim3(ga->params.islands), dim3(256), 0, stream,
              (const int32_t *)L.prio[0], (const int64_t *)L.obj[0], L.elite, L.elite_obj, K,
@@ -3051,17 +3055,17 @@ int ga_init_impl(ffs_ga *ga, const ffs_instance *in, const GaLayout &L, hipStrea
     return FFS_E_DEVICE;
   if (auto_cap) {
     // Later generations: generation 0's longest schedule plus 1/64 and 64 slots,
-    // then widened to the most slots (at most the sizing decode's) that keep as
-    // many waves per compute unit.
+    // then widened to the most slots (at most kAutoSlots) that keep as many waves
+    // per compute unit.
     Header host;
     if ((rc = read_header(L.hdr, &host, stream))) return rc;
-    const int64_t span = host.span_max;
+    const int64_t span = host.span_max, top = probe_cap(in, kAutoSlots);
     int64_t lo = (int64_t)align_up((size_t)(span + span / 64 + 64), 64);
-    if (lo > cap) lo = cap;
+    if (lo > top) lo = top;
     // the layout the generations will take at lo sets the bytes per slot count
     const bool narrow = hybrid && use_narrow<MAXM>(in, (int)lo, pop);
     const int w = waves_per_cu<MAXM>(lds_bytes_gen(in, (int)lo, narrow));
-    int64_t a = lo / 64, b = cap / 64;  // waves_per_cu falls as the slots grow
+    int64_t a = lo / 64, b = top / 64;  // waves_per_cu falls as the slots grow
     while (w > 0 && a < b) {
       const int64_t m = (a + b + 1) / 2;
       if (waves_per_cu<MAXM>(lds_bytes_gen(in, (int)(m * 64), narrow)) >= w)
