@@ -142,6 +142,25 @@ def test_ga_overflow_tier_in_the_loop():
     _same(_state(ga), st, "overflow GA")
 
 
+def test_ga_auto_size_beyond_the_sizing_decode():
+    """Schedules of 20 000-26 000 slots: generation 0's sizing decode keeps 16 384
+    slots on chip, so its decodes are redone off chip, and those redos record the
+    true lengths: later generations get more slots than the sizing decode had,
+    and the populations equal the oracle's."""
+    torch, ffsga = _ffs()
+    inst = W.random_instance(23, n_jobs=24, n_stages=3, machines=2, p_max=1500, percent=60)
+    gp = W.GaParams(2, 4, 8, mig_interval=2, mig_k=1)
+    _say("FFS_LDS_AUTO past the sizing decode's 16384 slots")
+    d = ffsga.DeviceInstance.from_host(inst)
+    ga = ffsga.GA(d, ffsga.GaConfig.of(gp, lds_slots=ffsga.FFS_LDS_AUTO), 5, 0, 0)
+    assert ga.overflows() > 0
+    assert 20000 < int(ga.ga.lds_slots) <= 32768, int(ga.ga.lds_slots)
+    ga.step(4)
+    ga.status()
+    st = oracle.ga_run(inst, gp, 5, 0, 0, 4)
+    _same(_state(ga), st, "auto size beyond the sizing decode")
+
+
 def test_ga_narrow_layout_with_inline_redo():
     """200 jobs, 6144 individuals and 5440-5760 on-chip slots (about 7.5 KB of LDS
     per wave): 16-bit ready times save 400 bytes a wave, which at some of these
