@@ -14,6 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1903_10741_amd", "libffsga.so")
 PEAKS_LIB = os.path.join(ROOT, "paper_1903_10741_amd", "libffspeaks.so")
 PEAKS_HEADERS = ("ffs_peaks.h",)
+FFS_E_INVAL, FFS_E_DEVICE = -1, -4  # include/ffsga.h
 
 
 def test_every_header_belongs_to_a_library():
@@ -67,3 +68,19 @@ def test_strerror_is_host_only():
     from paper_1903_10741_amd import ffsga
     assert "power" in ffsga.ffs_strerror(ffsga.FFS_E_INFEASIBLE)
     assert ffsga.ffs_strerror(0) == "ok"
+
+
+def test_island_group_setter_checks_its_argument():
+    """ga_set_island_groups rejects counts outside 0..4 before any device call, and
+    1 (every launch on the caller's stream) needs no streams: both run without a
+    GPU. The default (0) is restored afterwards; without a device that call can
+    only report FFS_E_DEVICE for the streams it could not create."""
+    lib = ctypes.CDLL(LIB)
+    lib.ga_set_island_groups.argtypes = [ctypes.c_int32]
+    lib.ga_set_island_groups.restype = ctypes.c_int
+    try:
+        assert lib.ga_set_island_groups(-1) == FFS_E_INVAL
+        assert lib.ga_set_island_groups(5) == FFS_E_INVAL
+        assert lib.ga_set_island_groups(1) == 0
+    finally:
+        assert lib.ga_set_island_groups(0) in (0, FFS_E_DEVICE)
