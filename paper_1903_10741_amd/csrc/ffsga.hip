@@ -151,6 +151,9 @@ __device__ __forceinline__ T ld_const(const T *p, size_t i) {
 
 // Profile with one byte per slot in LDS.
 struct LdsProfile {
+  // a commit adds each slot's byte from its own lane (the LDS serialises the
+  // four adds to one word), with no sum across a quad first
+  static constexpr bool kLaneAdds = true;
   uint8_t *p;
   int cap;
   __device__ void clear() const {
@@ -186,6 +189,9 @@ __host__ __device__ inline int offchip_cap(int horizon) {
 // profile belongs to one single-wave block, so work-group scope orders the
 // lanes' updates and reads; nothing else touches it.
 struct GlobalProfile {
+  // a commit sums each quad's bytes first and adds one word per quad (global
+  // atomics to one word from several lanes would queue at the cache)
+  static constexpr bool kLaneAdds = false;
   uint8_t *p;
   int cap;
   __device__ void clear() const {
@@ -247,17 +253,20 @@ __device__ __forceinline__ int place_bytes(const Prof &prof, int t0, int p, uint
 }
 
 // Commit q on [t, t + p) of a byte profile. The lanes cover the word-aligned
-// slots [base, base + 64): each quad of lanes holds one profile word, sums its
-// four byte increments (no carries: every byte stays <= Q_max) and its first
-// lane adds the word, so no two lanes add to one word (quads outside the window
-// add zero: cheaper than testing for it). Slots past cap (the
-// decode is then redone off chip) are clamped onto the last word, so the zero
-// slots after cap stay zero.
+// slots [base, base + 64), lane i slot base + i. Bytes never carry into each
+// other (every byte stays <= Q_max), so a word may take its four slots'
+// increments as four adds or as one: on chip each lane of the window adds its
+// own byte; off chip each quad of lanes sums its bytes across the quad and its
+// first lane adds the word (quads outside the window add zero: cheaper than
+// testing for it). Slots past cap (the decode is then redone off chip) are
+// clamped onto the last word, so the zero slots after cap stay zero.
 //
-// In two halves: commit_word forms each quad's word increment (registers only),
-// commit_add adds them; an op loop can place independent work between the two.
+// In two halves: commit_word forms the increments (registers only), commit_add
+// adds them; an op loop can place independent work between the two.
+template <class Prof>
 __device__ __forceinline__ uint32_t commit_word(int t, int p, int q) {
   const int lane = __lane_id();
+  if (Prof::kLaneAdds) return (uint32_t)q << (8 * (lane & 3));  // commit_add masks the window
   const int base = t & ~3;
   uint32_t c = (uint32_t)(base + lane - t) < (uint32_t)p ? (uint32_t)q << (8 * (lane & 3)) : 0u;
   c += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)c, 0xB1, 0xF, 0xF, false);
@@ -268,14 +277,18 @@ template <class Prof>
 __device__ __forceinline__ void commit_add(const Prof &prof, int t, int p, int q, uint32_t c) {
   const int lane = __lane_id(), cap = prof.cap;
   const int base = t & ~3;
-  if ((lane & 3) == 0) prof.add_word(min(base + lane, cap - 4), c);
+  if (Prof::kLaneAdds) {
+    if ((uint32_t)(base + lane - t) < (uint32_t)p) prof.add_word(min(base + (lane & ~3), cap - 4), c);
+  } else if ((lane & 3) == 0) {
+    prof.add_word(min(base + lane, cap - 4), c);
+  }
   if (__builtin_expect(t - base + p > kWave, 0))  // windows longer than the lanes
     for (int b = base + kWave + lane; b < t + p; b += kWave) prof.add(min(b, cap - 1), (uint32_t)q);
   prof.order();
 }
 template <class Prof>
 __device__ __forceinline__ void commit_bytes(const Prof &prof, int t, int p, int q) {
-  commit_add(prof, t, p, q, commit_word(t, p, q));
+  commit_add(prof, t, p, q, commit_word<Prof>(t, p, q));
 }
 
 __device__ __forceinline__ int LdsProfile::place(int t0, int p, uint32_t thr) const {
@@ -609,7 +622,7 @@ __device__ int decode_core_rules(const DInst &I, const L &l, Prof &&prof, int64_
       const int ex_next = *rdy_next;
       const uint32_t pq_next = *recp;
       // the previous op's profile words, formed while this op's keys reduce
-      const uint32_t cword = commit_word(ct, cp, cq);
+      const uint32_t cword = commit_word<typename std::decay<decltype(prof)>::type>(ct, cp, cq);
       // Machine of earliest completion (ties to the lowest index).
       const int t0v = max(ex, fr);  // earliest start on this lane's machine
       const uint32_t key = ((uint32_t)(t0v + (int)(pqv & 0xFFFFu)) << 4) | (uint32_t)lane;
